@@ -1,0 +1,215 @@
+/*
+ * hcov -- H-matrix Gaussian log-likelihood of a Matérn random field on an
+ * AMD Instinct MI355X (gfx950).  C ABI: plain pointers and sizes only.
+ *
+ * The method is the one of Litvinenko, Kriemann, Genton, Sun and Keyes,
+ * "HLIBCov: Parallel hierarchical matrix approximation of large covariance
+ * matrices and likelihoods with applications in parameter identification",
+ * arXiv:1709.08625 (cited below as [HLIBCov]):
+ *   - joint Gaussian log-likelihood, Eq. (1) of Sec. 1;
+ *   - its H-matrix form through the H-Cholesky factor, Eq. (2) of Sec. 1;
+ *   - Matérn covariance, Eq. (3) of Sec. 2.1, theta = (ell, nu, sigma^2);
+ *   - cluster tree / block cluster tree / admissibility, Sec. 2.2 and
+ *     Appendix A (standard admissibility Adm_eta);
+ *   - fixed-accuracy low-rank blocks ||M - M~|| <= eps ||M||, Sec. 2.2;
+ *   - ACA with SVD recompression, the remark at the end of Appendix B;
+ *   - nugget tau^2 added to the diagonal, Sec. 4 and Sec. 5.2.
+ *
+ * Conventions for every call:
+ *   - Return value: HCOV_OK (0) or a negative error code; hcov_strerror()
+ *     names it and hcov_last_error() holds a message for the context.  No C++
+ *     exception crosses this boundary.
+ *   - Vectors z, x passed to the context are in the caller's (external) point
+ *     order; the library applies its cluster permutation internally.
+ *   - "where" arguments: HCOV_HOST (host memory) or HCOV_DEVICE (device
+ *     memory on the context's GPU).
+ *   - A context is not thread safe; distinct contexts are independent.  All
+ *     device work of a context is ordered on its HIP stream.
+ *   - Device memory of a context comes from the allocator callbacks in
+ *     hcov_opts when given (e.g. the PyTorch caching allocator), else from
+ *     hipMalloc; it is released by hcov_destroy.
+ */
+#ifndef HCOV_H_
+#define HCOV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ return codes */
+#define HCOV_OK 0
+#define HCOV_EINVAL -1      /* argument out of its domain (theta, eps, n, ...) */
+#define HCOV_ENOTSPD -2     /* non-positive or non-finite pivot in H-Cholesky */
+#define HCOV_ENOMEM -3      /* device or host allocation failed / over cap */
+#define HCOV_ESTATE -4      /* call out of order (e.g. logdet before cholesky) */
+#define HCOV_EDEVICE -5     /* HIP runtime error or no device */
+#define HCOV_ERANK -6       /* a low-rank block needed more than max_rank */
+
+#define HCOV_HOST 0
+#define HCOV_DEVICE 1
+
+#define HCOV_FP64 0         /* every step in FP64 */
+#define HCOV_MIXED 1        /* low-rank factors/updates FP32; diagonal, logdet, quad FP64 */
+
+/* Matérn parameters, Eq. (3) [HLIBCov Sec. 2.1], with named fields:
+ * sigma2 = sigma^2 > 0 (variance), ell > 0 (range; the kernel argument is
+ * h/ell exactly as in Eq. (3)), nu > 0 (smoothness), nugget = tau^2 >= 0
+ * added to the diagonal only [HLIBCov Sec. 5.2]. */
+typedef struct {
+  double sigma2;
+  double ell;
+  double nu;
+  double nugget;
+} hcov_theta;
+
+typedef void* (*hcov_alloc_fn)(size_t bytes, void* user);
+typedef void (*hcov_free_fn)(void* ptr, void* user);
+
+/* Build options (all fields have defaults through hcov_opts_default). */
+typedef struct {
+  int precision;          /* HCOV_FP64 (default) or HCOV_MIXED */
+  int max_rank;           /* capacity of every low-rank block (default 64) */
+  double aca_eps_factor;  /* ACA stops at aca_eps_factor*eps before the SVD
+                             recompression (default 0.1) */
+  int fuse_solve;         /* 1: hcov_loglik solves L v = z inside the
+                             factorisation sweep (default 1) */
+  size_t mem_cap_bytes;   /* 0 = no cap; builds whose estimate exceeds it fail
+                             with HCOV_ENOMEM */
+  hcov_alloc_fn alloc;    /* optional device allocator; NULL = hipMalloc */
+  hcov_free_fn free;
+  void* alloc_user;
+} hcov_opts;
+
+/* Structure and work counters of a context (see hcov_stats). */
+typedef struct {
+  int64_t n;
+  int leaf;
+  int depth;                  /* cluster-tree depth D (2^D leaves) */
+  int64_t n_dense_blocks;
+  int64_t n_lr_blocks;
+  int64_t dense_entries;      /* stored entries of dense blocks */
+  int64_t lr_rows;            /* sum over low-rank blocks of (rows + cols) */
+  int max_rank_seen;          /* largest rank after the last assembly/factorisation */
+  double mean_rank;
+  int64_t bytes_device;       /* device memory held by the context */
+  int64_t bytes_factor;       /* bytes of the stored factor (actual ranks) */
+  double ms_tree, ms_assemble, ms_factor, ms_solve;   /* last phase times */
+  int64_t n_steps;            /* sweep steps of the factorisation (= 2^D) */
+  int64_t n_launches_factor;  /* kernel launches of one factorisation */
+} hcov_stats_t;
+
+typedef struct hcov_ctx hcov_ctx;
+
+/* Fill *o with the defaults listed above. */
+void hcov_opts_default(hcov_opts* o);
+
+/* hcov_build -- cluster tree, block cluster tree and H-matrix assembly.
+ *
+ * Defines the problem of [HLIBCov Sec. 1]: n locations s_i in R^2 and the
+ * Matérn covariance of Eq. (3).  Builds on the GPU
+ *   - the cluster tree: recursive bisection of the index set into two
+ *     equal-sized subsets [HLIBCov Sec. 2.2] by an axis-parallel cut across
+ *     the longer side of each cluster's bounding box, down to leaves of at
+ *     most `leaf` points (n_min of Sec. 2.2);
+ *   - the block cluster tree with standard admissibility Adm_eta
+ *     [HLIBCov Appendix A, Eq. (stand_cond)];
+ *   - the H-matrix C~(theta): dense leaves exactly, admissible leaves by ACA
+ *     followed by SVD recompression to ||M - M~|| <= eps ||M||
+ *     [HLIBCov Sec. 2.2 and Appendix B remark].
+ *
+ * locs_xy : host pointer, n x 2 doubles, row major (x0, y0, x1, y1, ...);
+ *           copied; must be finite.
+ * n       : number of locations, >= 1.
+ * theta   : see hcov_theta; sigma2, ell, nu > 0, nugget >= 0.
+ * eps     : block accuracy in (0, 1).
+ * leaf    : leaf size in [2, 128].
+ * eta     : admissibility parameter > 0.
+ * opts    : NULL for defaults.
+ * hip_stream : hipStream_t to order all work on (NULL = default stream).
+ * out     : receives the new context (NULL on error).
+ */
+int hcov_build(const double* locs_xy, int64_t n, hcov_theta theta, double eps,
+               int leaf, double eta, const hcov_opts* opts, void* hip_stream,
+               hcov_ctx** out);
+
+/* Re-assemble C~ for new parameters, reusing both trees [HLIBCov Appendix B:
+ * every likelihood evaluation rebuilds the matrix for its theta].  Invalidates
+ * the factor. */
+int hcov_set_theta(hcov_ctx* ctx, hcov_theta theta);
+
+/* H-Cholesky C~ = L~ L~^T in place [HLIBCov Eq. (2), Sec. 2.2: H-matrix
+ * factorisation with the same fixed accuracy eps for the factor].  Returns
+ * HCOV_ENOTSPD if a diagonal leaf has a non-positive or non-finite pivot. */
+int hcov_cholesky(hcov_ctx* ctx);
+
+/* log|C~| = 2 sum_i log L~_ii [HLIBCov Eq. (2)], FP64 reduction in a fixed
+ * order.  Requires hcov_cholesky (else HCOV_ESTATE). */
+int hcov_logdet(hcov_ctx* ctx, double* out_logdet);
+
+/* x = (L~ L~^T)^{-1} z: forward solve L~ v = z [HLIBCov Eq. (2)] then the
+ * backward solve L~^T x = v.  z and x hold n doubles in external order, both
+ * on the host or both on the device (`where`).  Requires hcov_cholesky. */
+int hcov_solve(hcov_ctx* ctx, const double* z, double* x, int where);
+
+/* Forward solve only: v = L~^{-1} P z (v in cluster order) and
+ * quad = v^T v.  v may be NULL. */
+int hcov_forward(hcov_ctx* ctx, const double* z, double* v, double* quad, int where);
+
+/* y = P^T L~ xi: sample a field with covariance L~ L~^T from a standard
+ * normal xi given in cluster order [HLIBCov Sec. 5.1 generates Z0 = L~ xi].
+ * Result in external order.  Requires hcov_cholesky. */
+int hcov_sample(hcov_ctx* ctx, const double* xi, double* y, int where);
+
+/* y = C~ x (H-matrix times vector, [HLIBCov Table 1 "C~ z"]), external order.
+ * Requires an assembled, not yet factorised context (else HCOV_ESTATE). */
+int hcov_matvec(hcov_ctx* ctx, const double* x, double* y, int where);
+
+/* H-log-likelihood of Eq. (2) [HLIBCov Sec. 1]:
+ *   L~ = -n/2 log(2 pi) - sum_i log L~_ii - 1/2 v^T v,  L~ v = z,
+ * returned with the paper's sign (+L; the listing of Appendix B returns -L
+ * for minimisation).  Runs hcov_cholesky when the factor is not current.
+ * out_logdet (log|C~|) and out_quad (z^T C~^{-1} z) may be NULL. */
+int hcov_loglik(hcov_ctx* ctx, const double* z, int where, double* out_ll,
+                double* out_logdet, double* out_quad);
+
+/* Structure, memory and per-phase time counters. */
+int hcov_stats(const hcov_ctx* ctx, hcov_stats_t* out);
+
+/* Conservative device-memory bound of hcov_build + hcov_cholesky for n
+ * points at this leaf size and rank capacity, from sizes alone (no tree is
+ * built): dense near-field leaves ~ 16 n leaf, low-rank factors
+ * ~ 24 n (D+1) max_rank, plus scratch.  Used for admission control in
+ * serving; the exact figure after a build is hcov_stats().bytes_device. */
+int hcov_estimate_bytes(const double* locs_xy, int64_t n, double eps, int leaf,
+                        double eta, const hcov_opts* opts, size_t* out_bytes);
+
+/* Cluster permutation: perm[i] = external index of cluster-order position i. */
+int hcov_perm(const hcov_ctx* ctx, int64_t* perm);
+
+void hcov_destroy(hcov_ctx* ctx);
+
+/* Eq. (3) on the device for n given distances h (host arrays): test access to
+ * the device Matérn / K_nu evaluation used by the assembly. */
+int hcov_matern_eval(hcov_theta theta, const double* h, double* out, int64_t n);
+
+const char* hcov_strerror(int code);
+const char* hcov_last_error(const hcov_ctx* ctx);
+
+/* ------------------------------------------------------------ tree access
+ * Structural output for bit-exact checks against the reference trees. */
+
+/* Depth D and the number of block-tree leaves. */
+int hcov_tree_sizes(const hcov_ctx* ctx, int* depth, int64_t* n_blocks);
+/* bbox: (2^(D+1)-1) x 4 doubles (xmin,xmax,ymin,ymax) in level order
+ * (level l node i at index 2^l-1+i); blocks: n_blocks x 4 int64 rows
+ * (level, row node, column node, kind) with kind 1 = low rank, 0 = dense, in
+ * breadth-first order. */
+int hcov_tree_dump(const hcov_ctx* ctx, double* bbox, int64_t* blocks);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HCOV_H_ */

@@ -1,0 +1,48 @@
+// Shared device/host helpers for the hcov HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.h"
+
+namespace hc {
+
+struct Bufs {
+  double* p[B_COUNT];
+};
+
+// Status bits written by kernels (device int status[0]); status[1] holds the
+// first failing cluster-order row of a non-SPD pivot (atomicMin).
+enum StatusBits : int {
+  STAT_RANK_OVERFLOW = 1,   // a block needed more than the rank capacity
+  STAT_SKETCH_SAT = 2,      // a randomised sketch showed no decay
+  STAT_NOT_SPD = 4,         // non-positive / non-finite pivot
+  STAT_NONFINITE = 8,       // non-finite matrix entry
+};
+
+__device__ __forceinline__ double* refp(const Bufs& b, const Ref& r) { return b.p[r.buf] + r.off; }
+
+__device__ __forceinline__ int dimv(const int* __restrict__ dyn, const Dim& d) {
+  if (d.slot < 0) return d.maxv;
+  int v = dyn[d.slot] + d.add;
+  return v < d.maxv ? v : d.maxv;
+}
+
+// Matérn parameters of Eq. (3) prepared on the host for one theta.
+struct MaternParams {
+  double sigma2;
+  double inv_ell;
+  double nu;
+  double nugget;
+  double norm;      // sigma2 * 2^(1-nu) / Gamma(nu)
+  double mu;        // nu - N, |mu| <= 1/2
+  double g1, g2;    // Temme's Gamma_1(mu), Gamma_2(mu)
+  double gp, gm;    // Gamma(1+mu), Gamma(1-mu)
+  double mupi;      // mu*pi / sin(mu*pi)
+  int N;            // round(nu)
+  int kind;         // 0 generic, 1: nu=1/2, 2: nu=3/2, 3: nu=5/2
+};
+
+}  // namespace hc

@@ -1,0 +1,62 @@
+// Host-side launch wrappers of the device kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "plan.h"
+
+namespace hc {
+
+struct FillJob {
+  int64_t off;
+  int64_t r0, c0;
+  int32_t p, q;
+  int32_t diag;
+  int32_t pad;
+};
+struct AcaJob {
+  int64_t off_u, off_v;
+  int64_t r0, c0;
+  int32_t p, q;
+  int32_t rank_slot;
+  int32_t pad;
+};
+
+// Device copies of the plan arrays and the run-time state a stage needs.
+struct LaunchCtx {
+  Bufs bufs;
+  int* dyn;
+  const GemmJob* gjobs;
+  const GemmProd* gprods;
+  const GemmTile* gtiles;
+  const TsqrSeg* tsegs;
+  const TsqrRed* treds;
+  const SmallJob* smalls;
+  const LeafJob* leafs;
+  const LeafTerm* lterms;
+  const TrsmJob* trsms;
+  const int2* copy_pairs;
+  int n_copy;
+  int rmax;
+  double eps;
+  double tau;
+  double* logdet;
+  int* status;
+};
+
+hipError_t setup_kernel_attributes();
+hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st);
+hipError_t launch_fill(double* D, const double* loc, const FillJob* jobs, int njobs,
+                       const MaternParams& P, hipStream_t st);
+hipError_t launch_aca(double* U, double* V, int* dyn, const double* loc, const AcaJob* jobs, int njobs,
+                      const MaternParams& P, double eps_aca, int kcap, int* status, hipStream_t st);
+hipError_t launch_permute(const double* in, double* out, const int* perm, int64_t n, int scatter,
+                          hipStream_t st);
+hipError_t launch_reduce(const double* x, int64_t n, int mode, double* part, hipStream_t st,
+                         int64_t* nparts);
+hipError_t launch_probe(const double* h, double* out, int64_t n, const MaternParams& P, hipStream_t st);
+hipError_t launch_gaussian(double* out, int64_t n, uint64_t seed, hipStream_t st);
+hipError_t launch_fill_value(double* out, int64_t n, double v, hipStream_t st);
+
+}  // namespace hc

@@ -1,0 +1,1025 @@
+// Planner: turns the cluster tree and block cluster tree into job lists.
+//
+// The factorisation is a left-looking H-Cholesky over the leaf clusters
+// c_0 .. c_{m-1} of a perfect binary cluster tree (Eq. (2) of Sec. 1; H-matrix
+// factorisation with the fixed accuracy eps of Sec. 2.2).  For a factor block
+// T = (rho, pi) the Cholesky identity gives
+//     L(rho,pi) = ( C(rho,pi) - L(rho, <pi) L(pi, <pi)^T ) L(pi,pi)^{-T},
+// where "<pi" are the columns before pi.  Those columns are the left
+// siblings K of the ancestors of pi that are right sons, so the update is a
+// sum of products L(rho,K) L(pi,K)^T; each product is expanded recursively on
+// the block tree until one side is a single low-rank or dense leaf, which
+// keeps every term of low rank.  The update is applied when the sweep reaches
+// the first leaf of pi; low-rank targets are then recompressed to accuracy
+// eps by a randomised range finder with exact QR-based truncation, and their
+// V factor is solved against L(pi,pi) one leaf row at a time as the sweep
+// passes through pi (forward substitution interleaved with the
+// factorisation, with the sibling blocks of the cluster tree applied as
+// H-matrix-vector products).
+#include "plan.h"
+
+#include <algorithm>
+#include <cassert>
+#include <cstdio>
+#include <functional>
+
+namespace hc {
+
+static const int TM = 64, TN = 64;   // GEMM tile (must match the kernel)
+static const int TSQR_SEG = 1024;    // rows per TSQR segment work-group
+static const int LEAF_MAX = 128;
+
+int64_t node_lo(const Plan& P, int l, int64_t i) { return P.lo[l][i]; }
+int64_t node_hi(const Plan& P, int l, int64_t i) { return P.lo[l][i + 1]; }
+
+namespace {
+
+struct Src {
+  Ref ref;
+  Dim cols;
+};
+
+struct Term {
+  int64_t r0, r1;   // absolute rows (inside the target's rows)
+  int64_t p0, p1;   // absolute rows of the V side (inside the target's cols)
+  Src U, V;
+};
+
+class Builder {
+ public:
+  Plan& P;
+  // per-step scratch bump allocator
+  int64_t scr_top = 0;
+  int32_t dyn_base = 0, dyn_top = 0, dyn_max = 0;
+  // current stage buffers (one step at a time)
+  struct GemmStage {
+    std::vector<int32_t> jobs;
+  };
+
+  explicit Builder(Plan& p) : P(p) {}
+
+  int64_t scr_alloc(int64_t elems) {
+    int64_t o = scr_top;
+    scr_top += (elems + 31) / 32 * 32;
+    if (scr_top > P.scr_elems) P.scr_elems = scr_top;
+    return o;
+  }
+  int32_t dyn_alloc() {
+    int32_t s = dyn_top++;
+    if (dyn_top > dyn_max) dyn_max = dyn_top;
+    return s;
+  }
+
+  // ---------------------------------------------------------------- GEMM
+  int32_t gemm_job(Ref C, Dim m, Dim n, int zero) {
+    GemmJob j{};
+    j.C = C;
+    j.m = m;
+    j.n = n;
+    j.zero = zero;
+    j.p0 = j.p1 = 0;
+    P.gjobs.push_back(j);
+    pending_prods.emplace_back();
+    return int32_t(P.gjobs.size() - 1);
+  }
+  // products are collected per job, then laid out contiguously at flush
+  std::vector<std::vector<GemmProd>> pending_prods;
+  int32_t job_base = 0;
+
+  void add_prod(int32_t job, Ref A, int ta, Ref B, int tb, Dim k, int i0, int j0, Dim mi,
+                Dim nj, double alpha) {
+    GemmProd p{};
+    p.A = A;
+    p.B = B;
+    p.ta = ta;
+    p.tb = tb;
+    p.k = k;
+    p.i0 = i0;
+    p.j0 = j0;
+    p.mi = mi;
+    p.nj = nj;
+    p.alpha = alpha;
+    pending_prods[job - job_base].push_back(p);
+  }
+
+  // close the GEMM jobs created since the last flush into one stage
+  void flush_gemm(std::vector<Stage>& out) {
+    int32_t nj = int32_t(P.gjobs.size()) - job_base;
+    if (nj <= 0) return;
+    int32_t t0 = int32_t(P.gtiles.size());
+    for (int32_t j = 0; j < nj; ++j) {
+      GemmJob& g = P.gjobs[job_base + j];
+      g.p0 = int32_t(P.gprods.size());
+      for (auto& p : pending_prods[j]) P.gprods.push_back(p);
+      g.p1 = int32_t(P.gprods.size());
+      int mt = (g.m.maxv + TM - 1) / TM, nt = (g.n.maxv + TN - 1) / TN;
+      for (int a = 0; a < mt; ++a)
+        for (int b = 0; b < nt; ++b) P.gtiles.push_back(GemmTile{job_base + j, a, b, 0});
+    }
+    pending_prods.clear();
+    job_base = int32_t(P.gjobs.size());
+    int32_t t1 = int32_t(P.gtiles.size());
+    if (t1 > t0) out.push_back(Stage{ST_GEMM, t0, t1});
+  }
+
+  // ---------------------------------------------------------------- TSQR
+  struct TsqrReq {
+    Ref X;
+    int64_t rows;
+    Dim cols;
+    Ref R;   // final R (ld rmax)
+  };
+  std::vector<TsqrReq> tsqr_pending;
+  void tsqr(Ref X, int64_t rows, Dim cols, Ref R) { tsqr_pending.push_back(TsqrReq{X, rows, cols, R}); }
+  void flush_tsqr(std::vector<Stage>& out) {
+    if (tsqr_pending.empty()) return;
+    int32_t s0 = int32_t(P.tsegs.size()), r0 = int32_t(P.treds.size());
+    const int64_t RR = int64_t(P.rmax) * P.rmax;
+    for (auto& q : tsqr_pending) {
+      int64_t nseg = (q.rows + TSQR_SEG - 1) / TSQR_SEG;
+      if (nseg <= 1) {
+        P.tsegs.push_back(TsqrSeg{q.X, int32_t(q.rows), q.cols, q.R});
+        continue;
+      }
+      int64_t base = scr_alloc(nseg * RR);
+      for (int64_t s = 0; s < nseg; ++s) {
+        Ref X = q.X;
+        X.off += s * TSQR_SEG;
+        int32_t rows = int32_t(std::min<int64_t>(TSQR_SEG, q.rows - s * TSQR_SEG));
+        P.tsegs.push_back(TsqrSeg{X, rows, q.cols, Ref{B_SCR, P.rmax, base + s * RR}});
+      }
+      P.treds.push_back(TsqrRed{Ref{B_SCR, P.rmax, base}, int32_t(nseg), q.cols, q.R});
+    }
+    tsqr_pending.clear();
+    int32_t s1 = int32_t(P.tsegs.size()), r1 = int32_t(P.treds.size());
+    if (s1 > s0) out.push_back(Stage{ST_TSQR_SEG, s0, s1});
+    if (r1 > r0) out.push_back(Stage{ST_TSQR_RED, r0, r1});
+  }
+
+  void flush_small(std::vector<Stage>& out, int32_t s0) {
+    int32_t s1 = int32_t(P.smalls.size());
+    if (s1 > s0) out.push_back(Stage{ST_SMALL, s0, s1});
+  }
+
+  // ---------------------------------------------------------------- tree helpers
+  int64_t lo(int l, int64_t i) const { return P.lo[l][i]; }
+  int64_t hi(int l, int64_t i) const { return P.lo[l][i + 1]; }
+  int32_t status(int l, int64_t a, int64_t c) const {
+    auto it = P.status.find(key3(l, a, c));
+    return it == P.status.end() ? -2 : it->second;
+  }
+  // region rows node (l,a) x cols node (lk,k): returns block id if covered by
+  // a single leaf, -1 if subdivided
+  int32_t region(int l, int64_t a, int lk, int64_t k) const {
+    int64_t aa = a >> (l - lk);
+    int32_t s = status(lk, aa, k);
+    if (s != -2) return s;
+    int ll = lk;
+    int64_t x = aa, y = k;
+    while (ll > 0) {
+      --ll;
+      x >>= 1;
+      y >>= 1;
+      int32_t t = status(ll, x, y);
+      if (t != -2) {
+        assert(t >= 0);
+        return t;
+      }
+    }
+    fprintf(stderr, "hcov plan: region lookup failed\n");
+    abort();
+  }
+
+  Dim rank_dim(int32_t b) const { return dim_dyn(P.blocks[b].rank_slot, P.kcap); }
+
+  // U of block b restricted to absolute rows [r0, r1)
+  Src lr_u(int32_t b, int64_t r0) const {
+    const BlockInfo& B = P.blocks[b];
+    return Src{Ref{B_U, int32_t(B.r1 - B.r0), B.off_u + (r0 - B.r0)}, rank_dim(b)};
+  }
+  Src lr_v(int32_t b, int64_t c0) const {
+    const BlockInfo& B = P.blocks[b];
+    return Src{Ref{B_V, int32_t(B.c1 - B.c0), B.off_v + (c0 - B.c0)}, rank_dim(b)};
+  }
+  // dense block b restricted to rows starting r0, cols starting c0, width w
+  Src dn(int32_t b, int64_t r0, int64_t c0, int w) const {
+    const BlockInfo& B = P.blocks[b];
+    int32_t ld = int32_t(B.r1 - B.r0);
+    return Src{Ref{B_DENSE, ld, B.off_d + (r0 - B.r0) + (c0 - B.c0) * ld}, dim_static(w)};
+  }
+
+  // W = L(P, K) X with P = (l,p), K = (lk,k); X has |K| rows (absolute
+  // column index c maps to X row c - K.lo).  Emits inner products into the
+  // current "A" stage and the accumulation job into the current "B" stage.
+  // Returns the scratch W (|P| x X.cols).
+  std::vector<int32_t>* stageA_jobs = nullptr;   // (unused, jobs are global)
+  struct Pending {
+    int32_t jobA_base;
+  };
+
+  // Two-phase GEMM emission: phase A jobs go to list A, phase B to list B.
+  struct Deferred {
+    Ref C;
+    Dim m, n;
+    int zero;
+    std::vector<GemmProd> prods;
+  };
+  std::vector<Deferred> listA, listB;
+
+  int32_t defer(std::vector<Deferred>& L, Ref C, Dim m, Dim n, int zero) {
+    L.push_back(Deferred{C, m, n, zero, {}});
+    return int32_t(L.size() - 1);
+  }
+  static void dprod(Deferred& d, Ref A, int ta, Ref B, int tb, Dim k, int i0, int j0, Dim mi,
+                    Dim nj, double alpha) {
+    GemmProd p{};
+    p.A = A;
+    p.B = B;
+    p.ta = ta;
+    p.tb = tb;
+    p.k = k;
+    p.i0 = i0;
+    p.j0 = j0;
+    p.mi = mi;
+    p.nj = nj;
+    p.alpha = alpha;
+    d.prods.push_back(p);
+  }
+  void emit(std::vector<Deferred>& L, std::vector<Stage>& out) {
+    for (auto& d : L) {
+      int32_t j = gemm_job(d.C, d.m, d.n, d.zero);
+      for (auto& p : d.prods)
+        add_prod(j, p.A, p.ta, p.B, p.tb, p.k, p.i0, p.j0, p.mi, p.nj, p.alpha);
+    }
+    L.clear();
+    flush_gemm(out);
+  }
+
+  // add to deferred job `d` (in list B) the contributions of region
+  // rows (l,p) x cols (lk,k) times X; W rows are offset by wrow0 = P.lo
+  void hmv_pieces(int l, int64_t p, int lk, int64_t k, const Src& X, int64_t xcol0,
+                  std::vector<Deferred>& LA, std::vector<Deferred>& LB, int32_t dB, double alpha,
+                  int64_t wrow0, bool transpose) {
+    int64_t P0 = lo(l, p), P1 = hi(l, p);
+    std::function<void(int, int64_t, int64_t)> rec = [&](int lv, int64_t r, int64_t c) {
+      int32_t s = status(lv, r, c);
+      if (s == -2) {
+        fprintf(stderr, "hcov plan: hmv lookup failed\n");
+        abort();
+      }
+      if (s >= 0) {
+        piece(s, std::max(lo(lv, r), P0), std::min(hi(lv, r), P1), lo(lv, c), hi(lv, c), X,
+              xcol0, LA, LB, dB, alpha, wrow0, transpose);
+        return;
+      }
+      std::vector<int64_t> rc;
+      if (lv < l)
+        rc.push_back(p >> (l - lv - 1));
+      else {
+        rc.push_back(2 * r);
+        rc.push_back(2 * r + 1);
+      }
+      for (int64_t rr : rc)
+        for (int64_t cc : {2 * c, 2 * c + 1}) rec(lv + 1, rr, cc);
+    };
+    int32_t st = region(l, p, lk, k);
+    if (st >= 0) {
+      piece(st, P0, P1, lo(lk, k), hi(lk, k), X, xcol0, LA, LB, dB, alpha, wrow0, transpose);
+      return;
+    }
+    rec(lk, p >> (l - lk), k);
+  }
+
+  // one leaf block b restricted to rows [r0,r1) x cols [c0,c1):
+  //   W[r0-wrow0 ..] += alpha * Lb[r, c] X[c - xcol0]
+  // transpose: W[c - wrow0] += alpha * Lb[r, c]^T X[r - xcol0]
+  void piece(int32_t b, int64_t r0, int64_t r1, int64_t c0, int64_t c1, const Src& X,
+             int64_t xcol0, std::vector<Deferred>& LA, std::vector<Deferred>& LB, int32_t dB,
+             double alpha, int64_t wrow0, bool transpose) {
+    const BlockInfo& B = P.blocks[b];
+    int nr = int(r1 - r0), nc = int(c1 - c0);
+    if (nr <= 0 || nc <= 0) return;
+    if (!transpose) {
+      if (B.kind == 1) {
+        // T = V_b[c]^T X[c]  (rank x X.cols)
+        Src V = lr_v(b, c0);
+        int64_t t = scr_alloc(int64_t(P.kcap) * X.cols.maxv);
+        int32_t dA = defer(LA, Ref{B_SCR, P.kcap, t}, rank_dim(b), X.cols, 1);
+        Ref Xr = X.ref;
+        Xr.off += (c0 - xcol0);
+        dprod(LA[dA], V.ref, 1, Xr, 0, dim_static(nc), 0, 0, rank_dim(b), X.cols, 1.0);
+        Src U = lr_u(b, r0);
+        dprod(LB[dB], U.ref, 0, Ref{B_SCR, P.kcap, t}, 0, rank_dim(b), int(r0 - wrow0), 0,
+              dim_static(nr), X.cols, alpha);
+      } else {
+        Src Dm = dn(b, r0, c0, nc);
+        Ref Xr = X.ref;
+        Xr.off += (c0 - xcol0);
+        dprod(LB[dB], Dm.ref, 0, Xr, 0, dim_static(nc), int(r0 - wrow0), 0, dim_static(nr),
+              X.cols, alpha);
+      }
+    } else {
+      if (B.kind == 1) {
+        Src U = lr_u(b, r0);
+        int64_t t = scr_alloc(int64_t(P.kcap) * X.cols.maxv);
+        int32_t dA = defer(LA, Ref{B_SCR, P.kcap, t}, rank_dim(b), X.cols, 1);
+        Ref Xr = X.ref;
+        Xr.off += (r0 - xcol0);
+        dprod(LA[dA], U.ref, 1, Xr, 0, dim_static(nr), 0, 0, rank_dim(b), X.cols, 1.0);
+        Src V = lr_v(b, c0);
+        dprod(LB[dB], V.ref, 0, Ref{B_SCR, P.kcap, t}, 0, rank_dim(b), int(c0 - wrow0), 0,
+              dim_static(nc), X.cols, alpha);
+      } else {
+        Src Dm = dn(b, r0, c0, nc);
+        Ref Xr = X.ref;
+        Xr.off += (r0 - xcol0);
+        dprod(LB[dB], Dm.ref, 1, Xr, 0, dim_static(nr), int(c0 - wrow0), 0, dim_static(nc),
+              X.cols, alpha);
+      }
+    }
+  }
+
+  // H-matvec producing a fresh scratch W = L(P,K) X
+  Src hmatvec(int l, int64_t p, int lk, int64_t k, const Src& X, int64_t xcol0) {
+    int64_t P0 = lo(l, p), P1 = hi(l, p);
+    int64_t w = scr_alloc((P1 - P0) * int64_t(X.cols.maxv));
+    int32_t dB = defer(listB, Ref{B_SCR, int32_t(P1 - P0), w}, dim_static(int(P1 - P0)), X.cols, 1);
+    hmv_pieces(l, p, lk, k, X, xcol0, listA, listB, dB, 1.0, P0, false);
+    return Src{Ref{B_SCR, int32_t(P1 - P0), w}, X.cols};
+  }
+
+  // terms of L(R,K) L(P,K)^T with R = (l,a), P = (l,p), K = (lk,k)
+  void pair_terms(int l, int64_t a, int64_t p, int lk, int64_t k, std::vector<Term>& out) {
+    int64_t R0 = lo(l, a), R1 = hi(l, a), Q0 = lo(l, p), Q1 = hi(l, p), K0 = lo(lk, k),
+            K1 = hi(lk, k);
+    int32_t sR = region(l, a, lk, k);
+    int32_t sP = region(l, p, lk, k);
+    int kR = sR >= 0 ? P.blocks[sR].kind : -1;
+    int kP = sP >= 0 ? P.blocks[sP].kind : -1;
+    if (kR == 1) {
+      Src Ua = lr_u(sR, R0);
+      Src Va = lr_v(sR, K0);
+      if (kP == 1) {
+        // U_t = Ua[R] (Va[K]^T Vb[K]),  V_t = Ub[P]
+        Src Vb = lr_v(sP, K0);
+        int64_t c = scr_alloc(int64_t(P.kcap) * P.kcap);
+        int32_t dA = defer(listA, Ref{B_SCR, P.kcap, c}, rank_dim(sR), rank_dim(sP), 1);
+        dprod(listA[dA], Va.ref, 1, Vb.ref, 0, dim_static(int(K1 - K0)), 0, 0, rank_dim(sR),
+              rank_dim(sP), 1.0);
+        int64_t u = scr_alloc((R1 - R0) * int64_t(P.kcap));
+        int32_t dB = defer(listB, Ref{B_SCR, int32_t(R1 - R0), u}, dim_static(int(R1 - R0)),
+                           rank_dim(sP), 1);
+        dprod(listB[dB], Ua.ref, 0, Ref{B_SCR, P.kcap, c}, 0, rank_dim(sR), 0, 0,
+              dim_static(int(R1 - R0)), rank_dim(sP), 1.0);
+        out.push_back(Term{R0, R1, Q0, Q1, Src{Ref{B_SCR, int32_t(R1 - R0), u}, rank_dim(sP)},
+                           lr_u(sP, Q0)});
+      } else {
+        Src W = hmatvec(l, p, lk, k, Va, K0);
+        out.push_back(Term{R0, R1, Q0, Q1, Ua, W});
+      }
+      return;
+    }
+    if (kP == 1) {
+      Src Vb = lr_v(sP, K0);
+      Src W = hmatvec(l, a, lk, k, Vb, K0);
+      out.push_back(Term{R0, R1, Q0, Q1, W, lr_u(sP, Q0)});
+      return;
+    }
+    if (kR == 0 && kP == 0) {
+      int w = int(K1 - K0);
+      out.push_back(Term{R0, R1, Q0, Q1, dn(sR, R0, K0, w), dn(sP, Q0, K0, w)});
+      return;
+    }
+    if (kR >= 0 || kP >= 0) {
+      fprintf(stderr, "hcov plan: dense/subdivided mix\n");
+      abort();
+    }
+    if (lk < l) {
+      pair_terms(l, a, p, lk + 1, 2 * k, out);
+      pair_terms(l, a, p, lk + 1, 2 * k + 1, out);
+    } else {
+      for (int64_t ai : {2 * a, 2 * a + 1})
+        for (int64_t pj : {2 * p, 2 * p + 1})
+          for (int64_t kc : {2 * k, 2 * k + 1}) pair_terms(l + 1, ai, pj, l + 1, kc, out);
+    }
+  }
+
+  std::vector<Term> update_terms(int l, int64_t a, int64_t b) {
+    std::vector<Term> out;
+    int lp = l;
+    int64_t node = b;
+    while (lp >= 1) {
+      if (node & 1) pair_terms(l, a, b, lp, node - 1, out);
+      node >>= 1;
+      --lp;
+    }
+    return out;
+  }
+
+  // ---------------------------------------------------------------- the sweep
+  void build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps);
+  void build_recompress();
+  void build_solves();
+  void build_matvec();
+};
+
+void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps) {
+  const int D = P.D;
+  const int64_t m = int64_t(1) << D;
+  std::vector<std::vector<int32_t>> by_start(m);
+  for (int32_t b = 0; b < int32_t(P.blocks.size()); ++b) {
+    const BlockInfo& B = P.blocks[b];
+    by_start[int64_t(B.c) << (D - B.level)].push_back(b);
+  }
+  // LR blocks whose column cluster contains leaf j are "active" at j
+  std::vector<std::vector<int32_t>> active(m);
+  std::unordered_map<uint64_t, std::vector<int32_t>> by_col;
+  for (int32_t b = 0; b < int32_t(P.blocks.size()); ++b) {
+    const BlockInfo& B = P.blocks[b];
+    if (B.kind != 1) continue;
+    int64_t f = int64_t(B.c) << (D - B.level), e = int64_t(B.c + 1) << (D - B.level);
+    for (int64_t x = f; x < e; ++x) active[x].push_back(b);
+    by_col[key3(B.level, B.c, 0)].push_back(b);
+  }
+  steps.assign(m, {});
+  const int RM = P.rmax;
+  const int64_t RR = int64_t(RM) * RM;
+  for (int64_t j = 0; j < m; ++j) {
+    std::vector<Stage>& st = steps[j];
+    scr_top = 0;
+    dyn_top = dyn_base;
+    const int64_t cj0 = lo(D, j), cj1 = hi(D, j);
+    const int pj = int(cj1 - cj0);
+
+    // ---- update terms of every target starting at j
+    struct LrT {
+      int32_t b;
+      std::vector<Term> terms;
+    };
+    std::vector<LrT> lrs;
+    std::vector<std::pair<int32_t, std::vector<Term>>> dns;
+    for (int32_t b : by_start[j]) {
+      const BlockInfo& B = P.blocks[b];
+      auto terms = update_terms(B.level, B.a, B.c);
+      if (B.kind == 1)
+        lrs.push_back(LrT{b, std::move(terms)});
+      else
+        dns.emplace_back(b, std::move(terms));
+    }
+    emit(listA, st);   // inner products and cores
+    emit(listB, st);   // W accumulation and U*core
+
+    // ---- randomised recompression of low-rank targets
+    if (!lrs.empty()) {
+      struct SK {
+        int32_t b;
+        int64_t p, q;
+        Dim r;          // sketch width
+        Dim rk;         // kept directions of Y
+        int64_t y, qm, bp, ry, rq, rb, pm, c2;
+        std::vector<int64_t> p1, z1;
+      };
+      std::vector<SK> sk(lrs.size());
+      for (size_t t = 0; t < lrs.size(); ++t) {
+        const BlockInfo& B = P.blocks[lrs[t].b];
+        SK& s = sk[t];
+        s.b = lrs[t].b;
+        s.p = B.r1 - B.r0;
+        s.q = B.c1 - B.c0;
+        int rmaxT = int(std::min<int64_t>({s.p, s.q, int64_t(P.rcap)}));
+        s.r = Dim{B.rank0_slot, P.oversample, rmaxT};
+        s.rk = dim_dyn(dyn_alloc(), rmaxT);
+        s.y = scr_alloc(s.p * rmaxT);
+        s.qm = scr_alloc(s.p * rmaxT);
+        s.bp = scr_alloc(s.q * rmaxT);
+        s.ry = scr_alloc(RR);
+        s.rq = scr_alloc(RR);
+        s.rb = scr_alloc(RR);
+        s.pm = scr_alloc(RR);
+        s.c2 = scr_alloc(RR);
+        // P1 = V^T Omega for A and each term
+        Dim kA = rank_dim(s.b);
+        int64_t pa = scr_alloc(int64_t(P.kcap) * rmaxT);
+        s.p1.push_back(pa);
+        int32_t d = defer(listA, Ref{B_SCR, P.kcap, pa}, kA, s.r, 1);
+        dprod(listA[d], Ref{B_V, int32_t(s.q), B.off_v}, 1, Ref{B_OMEGA, int32_t(P.omega_rows), 0},
+              0, dim_static(int(s.q)), 0, 0, kA, s.r, 1.0);
+        for (auto& T : lrs[t].terms) {
+          int kc = T.V.cols.maxv;
+          int64_t o = scr_alloc(int64_t(kc) * rmaxT);
+          s.p1.push_back(o);
+          int32_t dd = defer(listA, Ref{B_SCR, kc, o}, T.V.cols, s.r, 1);
+          dprod(listA[dd], T.V.ref, 1,
+                Ref{B_OMEGA, int32_t(P.omega_rows), T.p0 - B.c0}, 0,
+                dim_static(int(T.p1 - T.p0)), 0, 0, T.V.cols, s.r, 1.0);
+        }
+      }
+      emit(listA, st);
+      // Y = U_A P1_A - sum U_t P1_t
+      for (size_t t = 0; t < lrs.size(); ++t) {
+        const BlockInfo& B = P.blocks[sk[t].b];
+        SK& s = sk[t];
+        int32_t d = defer(listB, Ref{B_SCR, int32_t(s.p), s.y}, dim_static(int(s.p)), s.r, 1);
+        dprod(listB[d], Ref{B_U, int32_t(s.p), B.off_u}, 0, Ref{B_SCR, P.kcap, s.p1[0]}, 0,
+              rank_dim(s.b), 0, 0, dim_static(int(s.p)), s.r, 1.0);
+        for (size_t i = 0; i < lrs[t].terms.size(); ++i) {
+          auto& T = lrs[t].terms[i];
+          dprod(listB[d], T.U.ref, 0, Ref{B_SCR, T.V.cols.maxv, s.p1[i + 1]}, 0, T.U.cols,
+                int(T.r0 - B.r0), 0, dim_static(int(T.r1 - T.r0)), s.r, -1.0);
+        }
+      }
+      emit(listB, st);
+      // R_Y
+      for (auto& s : sk) tsqr(Ref{B_SCR, int32_t(s.p), s.y}, s.p, s.r, Ref{B_SCR, RM, s.ry});
+      flush_tsqr(st);
+      // P from SVD(R_Y)
+      int32_t sm0 = int32_t(P.smalls.size());
+      for (auto& s : sk) {
+        SmallJob J{};
+        J.kind = SK_SKETCH_P;
+        J.out_rank_slot = s.rk.slot;
+        J.k = s.r;
+        J.R1 = Ref{B_SCR, RM, s.ry};
+        J.C1 = Ref{B_SCR, RM, s.pm};
+        J.cap = s.rk.maxv;
+        J.sat = dim_static(-1);
+        J.eps = -2.0;           // tau from the context at run time
+        P.smalls.push_back(J);
+      }
+      flush_small(st, sm0);
+      // Q = Y P
+      for (auto& s : sk) {
+        int32_t d = defer(listA, Ref{B_SCR, int32_t(s.p), s.qm}, dim_static(int(s.p)), s.rk, 1);
+        dprod(listA[d], Ref{B_SCR, int32_t(s.p), s.y}, 0, Ref{B_SCR, RM, s.pm}, 0, s.r, 0, 0,
+              dim_static(int(s.p)), s.rk, 1.0);
+      }
+      emit(listA, st);
+      // Z1 = U^T Q for A and terms
+      for (size_t t = 0; t < lrs.size(); ++t) {
+        const BlockInfo& B = P.blocks[sk[t].b];
+        SK& s = sk[t];
+        int rmaxT = s.r.maxv;
+        int64_t za = scr_alloc(int64_t(P.kcap) * rmaxT);
+        s.z1.push_back(za);
+        int32_t d = defer(listA, Ref{B_SCR, P.kcap, za}, rank_dim(s.b), s.rk, 1);
+        dprod(listA[d], Ref{B_U, int32_t(s.p), B.off_u}, 1, Ref{B_SCR, int32_t(s.p), s.qm}, 0,
+              dim_static(int(s.p)), 0, 0, rank_dim(s.b), s.rk, 1.0);
+        for (auto& T : lrs[t].terms) {
+          int kc = T.U.cols.maxv;
+          int64_t o = scr_alloc(int64_t(kc) * rmaxT);
+          s.z1.push_back(o);
+          int32_t dd = defer(listA, Ref{B_SCR, kc, o}, T.U.cols, s.rk, 1);
+          dprod(listA[dd], T.U.ref, 1, Ref{B_SCR, int32_t(s.p), s.qm + (T.r0 - B.r0)}, 0,
+                dim_static(int(T.r1 - T.r0)), 0, 0, T.U.cols, s.rk, 1.0);
+        }
+      }
+      emit(listA, st);
+      // B' = V_A Z1_A - sum V_t Z1_t
+      for (size_t t = 0; t < lrs.size(); ++t) {
+        const BlockInfo& B = P.blocks[sk[t].b];
+        SK& s = sk[t];
+        int32_t d = defer(listB, Ref{B_SCR, int32_t(s.q), s.bp}, dim_static(int(s.q)), s.rk, 1);
+        dprod(listB[d], Ref{B_V, int32_t(s.q), B.off_v}, 0, Ref{B_SCR, P.kcap, s.z1[0]}, 0,
+              rank_dim(s.b), 0, 0, dim_static(int(s.q)), s.rk, 1.0);
+        for (size_t i = 0; i < lrs[t].terms.size(); ++i) {
+          auto& T = lrs[t].terms[i];
+          dprod(listB[d], T.V.ref, 0, Ref{B_SCR, T.U.cols.maxv, s.z1[i + 1]}, 0, T.V.cols,
+                int(T.p0 - B.c0), 0, dim_static(int(T.p1 - T.p0)), s.rk, -1.0);
+        }
+      }
+      emit(listB, st);
+      // R_Q and R_B'
+      for (auto& s : sk) {
+        tsqr(Ref{B_SCR, int32_t(s.p), s.qm}, s.p, s.rk, Ref{B_SCR, RM, s.rq});
+        tsqr(Ref{B_SCR, int32_t(s.q), s.bp}, s.q, s.rk, Ref{B_SCR, RM, s.rb});
+      }
+      flush_tsqr(st);
+      // C2 = R_Q^{-1} Z_k, new rank
+      sm0 = int32_t(P.smalls.size());
+      for (auto& s : sk) {
+        SmallJob J{};
+        J.kind = SK_SKETCH_F;
+        J.out_rank_slot = P.blocks[s.b].rank_slot;
+        J.k = s.rk;
+        J.R1 = Ref{B_SCR, RM, s.rb};
+        J.R2 = Ref{B_SCR, RM, s.rq};
+        J.C1 = Ref{B_SCR, RM, s.c2};
+        J.cap = P.kcap;
+        J.sat = s.r;            // saturation if rank == r
+        J.eps = -1.0;           // filled at run time from the context eps
+        P.smalls.push_back(J);
+      }
+      flush_small(st, sm0);
+      // U := Q C2, V := B' C2
+      for (auto& s : sk) {
+        const BlockInfo& B = P.blocks[s.b];
+        int32_t d = defer(listA, Ref{B_U, int32_t(s.p), B.off_u}, dim_static(int(s.p)),
+                          rank_dim(s.b), 1);
+        dprod(listA[d], Ref{B_SCR, int32_t(s.p), s.qm}, 0, Ref{B_SCR, RM, s.c2}, 0, s.rk, 0, 0,
+              dim_static(int(s.p)), rank_dim(s.b), 1.0);
+        int32_t d2 = defer(listA, Ref{B_V, int32_t(s.q), B.off_v}, dim_static(int(s.q)),
+                           rank_dim(s.b), 1);
+        dprod(listA[d2], Ref{B_SCR, int32_t(s.q), s.bp}, 0, Ref{B_SCR, RM, s.c2}, 0, s.rk, 0, 0,
+              dim_static(int(s.q)), rank_dim(s.b), 1.0);
+      }
+      emit(listA, st);
+    }
+
+    // ---- dense targets (incl. the diagonal leaf): update, potrf
+    {
+      int32_t l0 = int32_t(P.leafs.size());
+      for (auto& dt : dns) {
+        const BlockInfo& B = P.blocks[dt.first];
+        LeafJob J{};
+        J.D = Ref{B_DENSE, int32_t(B.r1 - B.r0), B.off_d};
+        J.p = int32_t(B.r1 - B.r0);
+        J.q = int32_t(B.c1 - B.c0);
+        J.diag = (B.a == B.c) ? 1 : 0;
+        J.leaf = int32_t(j);
+        J.row0 = B.r0;
+        J.t0 = int32_t(P.lterms.size());
+        for (auto& T : dt.second) {
+          LeafTerm L{};
+          L.U = T.U.ref;
+          L.V = T.V.ref;
+          L.k = T.U.cols;
+          L.i0 = int32_t(T.r0 - B.r0);
+          L.j0 = int32_t(T.p0 - B.c0);
+          L.mi = int32_t(T.r1 - T.r0);
+          L.nj = int32_t(T.p1 - T.p0);
+          P.lterms.push_back(L);
+        }
+        J.t1 = int32_t(P.lterms.size());
+        P.leafs.push_back(J);
+      }
+      int32_t l1 = int32_t(P.leafs.size());
+      if (l1 > l0) st.push_back(Stage{ST_LEAF, l0, l1});
+    }
+
+    // ---- triangular solves with L_jj
+    {
+      int32_t t0 = int32_t(P.trsms.size());
+      const BlockInfo& Dg = P.blocks[P.diag_block[j]];
+      Ref Lr{B_DENSE, pj, Dg.off_d};
+      auto add = [&](Ref X, int layout, Dim nc) {
+        for (int c0 = 0; c0 < nc.maxv; c0 += 64)
+          P.trsms.push_back(TrsmJob{Lr, pj, layout, X, nc, c0, std::min(64, nc.maxv - c0)});
+      };
+      for (auto& dt : dns) {
+        const BlockInfo& B = P.blocks[dt.first];
+        if (B.a == B.c) continue;
+        add(Ref{B_DENSE, int32_t(B.r1 - B.r0), B.off_d}, 1, dim_static(int(B.r1 - B.r0)));
+      }
+      for (int32_t b : active[j]) {
+        const BlockInfo& B = P.blocks[b];
+        add(Ref{B_V, int32_t(B.c1 - B.c0), B.off_v + (cj0 - B.c0)}, 0, rank_dim(b));
+      }
+      if (fuse_rhs) add(Ref{B_RHS, int32_t(P.rhs_ld), cj0}, 0, dim_static(1));
+      int32_t t1 = int32_t(P.trsms.size());
+      if (t1 > t0) st.push_back(Stage{ST_TRSM, t0, t1});
+    }
+
+    // ---- sibling update: the ancestor t1 whose last leaf is c_j, a left son
+    {
+      int lv = D;
+      int64_t node = j;
+      while (lv >= 1 && (node & 1) == 1) {
+        node >>= 1;
+        --lv;
+      }
+      if (lv >= 1) {
+        const int64_t t1 = node, t2 = node + 1;
+        const int64_t T1a = lo(lv, t1), T2a = lo(lv, t2), T2b = hi(lv, t2);
+        auto rhs = [&](Ref Xbase, int64_t xrow0, Dim cols) {
+          // X rows are indexed from absolute row xrow0
+          Src Xs{Xbase, cols};
+          Ref Out = Xbase;
+          Out.off += (T2a - xrow0);
+          int32_t dB = defer(listB, Out, dim_static(int(T2b - T2a)), cols, 0);
+          hmv_pieces(lv, t2, lv, t1, Xs, xrow0, listA, listB, dB, -1.0, T2a, false);
+        };
+        // targets whose column cluster is the parent of t1 or an ancestor of it
+        for (int lvl = lv - 1; lvl >= 0; --lvl) {
+          auto it = by_col.find(key3(lvl, t1 >> (lv - lvl), 0));
+          if (it == by_col.end()) continue;
+          for (int32_t b : it->second) {
+            const BlockInfo& B = P.blocks[b];
+            rhs(Ref{B_V, int32_t(B.c1 - B.c0), B.off_v}, B.c0, rank_dim(b));
+          }
+        }
+        if (fuse_rhs) rhs(Ref{B_RHS, int32_t(P.rhs_ld), 0}, 0, dim_static(1));
+        emit(listA, st);
+        emit(listB, st);
+      }
+    }
+  }
+  if (dyn_max > P.n_dyn) P.n_dyn = dyn_max;
+}
+
+// Assembly recompression of every low-rank block (ACA output in U, V with
+// rank0 columns): R_U, R_V by TSQR, SVD(R_U R_V^T), U := U C_U, V := V C_V.
+// Done in chunks so the R slots fit in the persistent scratch.
+void Builder::build_recompress() {
+  const int RM = P.rmax;
+  const int64_t RR = int64_t(RM) * RM;
+  std::vector<int32_t> lrb;
+  for (int32_t b = 0; b < int32_t(P.blocks.size()); ++b)
+    if (P.blocks[b].kind == 1) lrb.push_back(b);
+  const size_t CH = 2048;
+  int64_t pers_max = 0;
+  for (size_t c0 = 0; c0 < lrb.size(); c0 += CH) {
+    size_t c1 = std::min(lrb.size(), c0 + CH);
+    scr_top = 0;
+    // the R slots live in the persistent scratch; segment Rs in the step scratch
+    int64_t pers = 0;
+    std::vector<int64_t> ru(c1 - c0), rv(c1 - c0), cu(c1 - c0), cv(c1 - c0);
+    for (size_t i = c0; i < c1; ++i) {
+      ru[i - c0] = pers;
+      pers += RR;
+      rv[i - c0] = pers;
+      pers += RR;
+      cu[i - c0] = pers;
+      pers += RR;
+      cv[i - c0] = pers;
+      pers += RR;
+    }
+    pers_max = std::max(pers_max, pers);
+    for (size_t i = c0; i < c1; ++i) {
+      const BlockInfo& B = P.blocks[lrb[i]];
+      Dim k0 = dim_dyn(B.rank0_slot, P.kcap);
+      tsqr(Ref{B_U, int32_t(B.r1 - B.r0), B.off_u}, B.r1 - B.r0, k0, Ref{B_PERS, RM, ru[i - c0]});
+      tsqr(Ref{B_V, int32_t(B.c1 - B.c0), B.off_v}, B.c1 - B.c0, k0, Ref{B_PERS, RM, rv[i - c0]});
+    }
+    flush_tsqr(P.recomp_stages);
+    int32_t sm0 = int32_t(P.smalls.size());
+    for (size_t i = c0; i < c1; ++i) {
+      const BlockInfo& B = P.blocks[lrb[i]];
+      SmallJob J{};
+      J.kind = SK_RECOMP;
+      J.out_rank_slot = B.rank_slot;
+      J.k = dim_dyn(B.rank0_slot, P.kcap);
+      J.R1 = Ref{B_PERS, RM, ru[i - c0]};
+      J.R2 = Ref{B_PERS, RM, rv[i - c0]};
+      J.C1 = Ref{B_PERS, RM, cu[i - c0]};
+      J.C2 = Ref{B_PERS, RM, cv[i - c0]};
+      J.cap = P.kcap;
+      J.sat = dim_static(-1);
+      J.eps = -1.0;
+      P.smalls.push_back(J);
+    }
+    flush_small(P.recomp_stages, sm0);
+    for (size_t i = c0; i < c1; ++i) {
+      const BlockInfo& B = P.blocks[lrb[i]];
+      Dim k0 = dim_dyn(B.rank0_slot, P.kcap);
+      int32_t d = defer(listA, Ref{B_U, int32_t(B.r1 - B.r0), B.off_u},
+                        dim_static(int(B.r1 - B.r0)), rank_dim(lrb[i]), 1);
+      dprod(listA[d], Ref{B_U, int32_t(B.r1 - B.r0), B.off_u}, 0, Ref{B_PERS, RM, cu[i - c0]}, 0,
+            k0, 0, 0, dim_static(int(B.r1 - B.r0)), rank_dim(lrb[i]), 1.0);
+      int32_t d2 = defer(listA, Ref{B_V, int32_t(B.c1 - B.c0), B.off_v},
+                         dim_static(int(B.c1 - B.c0)), rank_dim(lrb[i]), 1);
+      dprod(listA[d2], Ref{B_V, int32_t(B.c1 - B.c0), B.off_v}, 0, Ref{B_PERS, RM, cv[i - c0]}, 0,
+            k0, 0, 0, dim_static(int(B.c1 - B.c0)), rank_dim(lrb[i]), 1.0);
+    }
+    emit(listA, P.recomp_stages);
+  }
+  P.recomp_stages.push_back(Stage{ST_COPY_RANK, 0, 0});
+  P.pers_elems = std::max(P.pers_elems, pers_max);
+}
+
+// Forward (L v = z) and backward (L^T x = v) substitution on B_RHS col 0.
+void Builder::build_solves() {
+  const int D = P.D;
+  const int64_t m = int64_t(1) << D;
+  P.fsolve_steps.assign(m, {});
+  P.bsolve_steps.assign(m, {});
+  Ref X{B_RHS, int32_t(P.rhs_ld), 0};
+  for (int64_t j = 0; j < m; ++j) {
+    auto& st = P.fsolve_steps[j];
+    scr_top = 0;
+    int64_t c0 = lo(D, j);
+    int pj = int(hi(D, j) - c0);
+    int32_t t0 = int32_t(P.trsms.size());
+    P.trsms.push_back(TrsmJob{Ref{B_DENSE, pj, P.blocks[P.diag_block[j]].off_d}, pj, 0,
+                              Ref{B_RHS, int32_t(P.rhs_ld), c0}, dim_static(1), 0, 1});
+    st.push_back(Stage{ST_TRSM, t0, t0 + 1});
+    int lv = D;
+    int64_t node = j;
+    while (lv >= 1 && (node & 1) == 1) {
+      node >>= 1;
+      --lv;
+    }
+    if (lv >= 1) {
+      int64_t t1 = node, t2 = node + 1;
+      int64_t T2a = lo(lv, t2), T2b = hi(lv, t2);
+      Ref Out = X;
+      Out.off += T2a;
+      int32_t dB = defer(listB, Out, dim_static(int(T2b - T2a)), dim_static(1), 0);
+      hmv_pieces(lv, t2, lv, t1, Src{X, dim_static(1)}, 0, listA, listB, dB, -1.0, T2a, false);
+      emit(listA, st);
+      emit(listB, st);
+    }
+  }
+  // backward: j descending; x_j = L_jj^{-T} v_j; then for the ancestor t2
+  // whose first leaf is c_j and which is a right son: v[t1] -= L(t2,t1)^T x[t2]
+  for (int64_t jj = m - 1; jj >= 0; --jj) {
+    auto& st = P.bsolve_steps[m - 1 - jj];
+    scr_top = 0;
+    int64_t c0 = lo(D, jj);
+    int pj = int(hi(D, jj) - c0);
+    int32_t t0 = int32_t(P.trsms.size());
+    P.trsms.push_back(TrsmJob{Ref{B_DENSE, pj, P.blocks[P.diag_block[jj]].off_d}, pj, 2,
+                              Ref{B_RHS, int32_t(P.rhs_ld), c0}, dim_static(1), 0, 1});
+    st.push_back(Stage{ST_TRSM, t0, t0 + 1});
+    int lv = D;
+    int64_t node = jj;
+    while (lv >= 1 && (node & 1) == 0) {
+      node >>= 1;
+      --lv;
+    }
+    if (lv >= 1) {
+      int64_t t2 = node, t1 = node - 1;
+      int64_t T1a = lo(lv, t1), T1b = hi(lv, t1);
+      Ref Out = X;
+      Out.off += T1a;
+      int32_t dB = defer(listB, Out, dim_static(int(T1b - T1a)), dim_static(1), 0);
+      hmv_pieces(lv, t2, lv, t1, Src{X, dim_static(1)}, 0, listA, listB, dB, -1.0, T1a, true);
+      emit(listA, st);
+      emit(listB, st);
+    }
+  }
+}
+
+// y = C~ x on the assembled matrix (x = B_RHS col 0, y = col 1), and
+// y = L~ x on the factor.  Output rows are split by leaf cluster so every
+// job owns its rows.
+void Builder::build_matvec() {
+  const int D = P.D;
+  const int64_t m = int64_t(1) << D;
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<Stage>& out = pass == 0 ? P.matvec_stages : P.lmul_stages;
+    scr_top = 0;
+    Ref X{B_RHS, int32_t(P.rhs_ld), 0};
+    std::vector<int32_t> jobB(m);
+    for (int64_t j = 0; j < m; ++j) {
+      Ref Y{B_RHS, int32_t(P.rhs_ld), P.rhs_ld + lo(D, j)};
+      jobB[j] = defer(listB, Y, dim_static(int(hi(D, j) - lo(D, j))), dim_static(1), 1);
+    }
+    for (int32_t b = 0; b < int32_t(P.blocks.size()); ++b) {
+      const BlockInfo& B = P.blocks[b];
+      // leaf rows covered by the block rows / cols
+      auto leaf_of = [&](int64_t r) {
+        // leaf containing absolute row r (leaves are contiguous, sizes differ by <= 1)
+        int64_t lo_ = 0, hi_ = m - 1;
+        while (lo_ < hi_) {
+          int64_t mid = (lo_ + hi_ + 1) / 2;
+          if (lo(D, mid) <= r) lo_ = mid; else hi_ = mid - 1;
+        }
+        return lo_;
+      };
+      bool diag = (B.a == B.c);
+      for (int side = 0; side < 2; ++side) {
+        if (side == 1 && diag) break;   // diagonal tiles hold both triangles (C) / lower (L)
+        if (side == 1 && pass == 1) break;   // L x uses the lower part only
+        // side 0: y[rows] += M x[cols]; side 1: y[cols] += M^T x[rows]
+        int64_t o0 = side == 0 ? B.r0 : B.c0, o1 = side == 0 ? B.r1 : B.c1;
+        int64_t i0 = side == 0 ? B.c0 : B.r0, i1 = side == 0 ? B.c1 : B.r1;
+        int64_t tmp = -1;
+        if (B.kind == 1) {
+          tmp = scr_alloc(P.kcap);
+          int32_t dA = defer(listA, Ref{B_SCR, P.kcap, tmp}, rank_dim(b), dim_static(1), 1);
+          Ref inner = side == 0 ? Ref{B_V, int32_t(B.c1 - B.c0), B.off_v}
+                                : Ref{B_U, int32_t(B.r1 - B.r0), B.off_u};
+          Ref xs = X;
+          xs.off += i0;
+          dprod(listA[dA], inner, 1, xs, 0, dim_static(int(i1 - i0)), 0, 0, rank_dim(b),
+                dim_static(1), 1.0);
+        }
+        for (int64_t L = leaf_of(o0); L < m && lo(D, L) < o1; ++L) {
+          int64_t a = std::max(o0, lo(D, L)), e = std::min(o1, hi(D, L));
+          Deferred& dj = listB[jobB[L]];
+          if (B.kind == 1) {
+            Ref outer = side == 0 ? Ref{B_U, int32_t(B.r1 - B.r0), B.off_u + (a - B.r0)}
+                                  : Ref{B_V, int32_t(B.c1 - B.c0), B.off_v + (a - B.c0)};
+            dprod(dj, outer, 0, Ref{B_SCR, P.kcap, tmp}, 0, rank_dim(b), int(a - lo(D, L)), 0,
+                  dim_static(int(e - a)), dim_static(1), 1.0);
+          } else {
+            int32_t ld = int32_t(B.r1 - B.r0);
+            Ref xs = X;
+            xs.off += i0;
+            if (side == 0)
+              dprod(dj, Ref{B_DENSE, ld, B.off_d + (a - B.r0)}, 0, xs, 0,
+                    dim_static(int(i1 - i0)), int(a - lo(D, L)), 0, dim_static(int(e - a)),
+                    dim_static(1), 1.0);
+            else
+              dprod(dj, Ref{B_DENSE, ld, B.off_d + (a - B.c0) * ld}, 1, xs, 0,
+                    dim_static(int(i1 - i0)), int(a - lo(D, L)), 0, dim_static(int(e - a)),
+                    dim_static(1), 1.0);
+          }
+        }
+      }
+    }
+    emit(listA, out);
+    emit(listB, out);
+  }
+}
+
+}  // namespace
+
+std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, int64_t nb,
+                       int kcap, int oversample, bool mixed) {
+  (void)mixed;
+  P = Plan();
+  P.n = n;
+  P.D = D;
+  P.leaf = leaf;
+  P.kcap = kcap;
+  P.oversample = oversample;
+  P.rcap = kcap + oversample;
+  P.rmax = std::max(P.rcap, kcap);
+  if (kcap > 64 || kcap < 1) return "rank capacity must be in [1, 64]";
+  if (P.rmax > 96) return "rank capacity plus oversampling must not exceed 96";
+  // node ranges: left son takes ceil(s/2)
+  P.lo.resize(D + 1);
+  P.lo[0] = {0, n};
+  for (int l = 1; l <= D; ++l) {
+    auto& prev = P.lo[l - 1];
+    auto& cur = P.lo[l];
+    int64_t cnt = int64_t(1) << (l - 1);
+    cur.resize(2 * cnt + 1);
+    for (int64_t i = 0; i < cnt; ++i) {
+      int64_t a = prev[i], b = prev[i + 1];
+      cur[2 * i] = a;
+      cur[2 * i + 1] = a + (b - a + 1) / 2;
+    }
+    cur[2 * cnt] = n;
+  }
+  int64_t m = int64_t(1) << D;
+  for (int64_t i = 0; i < m; ++i)
+    if (P.lo[D][i + 1] - P.lo[D][i] > LEAF_MAX) return "leaf larger than 128";
+  P.blocks.resize(nb);
+  P.diag_block.assign(m, -1);
+  int32_t dyn = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    BlockInfo& B = P.blocks[b];
+    B.level = int32_t(blk[4 * b]);
+    B.a = int32_t(blk[4 * b + 1]);
+    B.c = int32_t(blk[4 * b + 2]);
+    B.kind = int32_t(blk[4 * b + 3]);
+    B.r0 = P.lo[B.level][B.a];
+    B.r1 = P.lo[B.level][B.a + 1];
+    B.c0 = P.lo[B.level][B.c];
+    B.c1 = P.lo[B.level][B.c + 1];
+    int64_t p = B.r1 - B.r0, q = B.c1 - B.c0;
+    if (B.kind == 1) {
+      B.off_u = P.u_elems;
+      P.u_elems += p * kcap;
+      B.off_v = P.v_elems;
+      P.v_elems += q * kcap;
+      B.off_d = -1;
+      B.rank_slot = dyn++;
+      B.rank0_slot = dyn++;
+      P.n_lr++;
+      P.lr_rows += p + q;
+    } else {
+      B.off_d = P.dense_elems;
+      P.dense_elems += p * q;
+      B.off_u = B.off_v = -1;
+      B.rank_slot = B.rank0_slot = -1;
+      P.n_dense++;
+      if (B.level != D) return "dense block above the leaf level";
+      if (B.a == B.c) P.diag_block[B.a] = int32_t(b);
+    }
+    P.status[key3(B.level, B.a, B.c)] = int32_t(b);
+    int l = B.level;
+    int64_t x = B.a, y = B.c;
+    while (l > 0) {
+      --l;
+      x >>= 1;
+      y >>= 1;
+      uint64_t k = key3(l, x, y);
+      if (P.status.count(k)) break;
+      P.status[k] = -1;
+    }
+  }
+  for (int64_t i = 0; i < m; ++i)
+    if (P.diag_block[i] < 0) return "missing diagonal leaf";
+  P.rhs_ld = n;
+  P.omega_rows = std::max<int64_t>(n, 1);
+  Builder Bd(P);
+  Bd.dyn_base = dyn;
+  Bd.dyn_top = dyn;
+  Bd.dyn_max = dyn;
+  P.n_dyn = dyn;
+  Bd.build_recompress();
+  Bd.build_steps(true, P.steps);
+  Bd.build_steps(false, P.steps_nofuse);
+  Bd.build_solves();
+  Bd.build_matvec();
+  if (Bd.dyn_max > P.n_dyn) P.n_dyn = Bd.dyn_max;
+  int64_t launches = 0;
+  for (auto& s : P.steps) launches += int64_t(s.size());
+  P.n_launch_fact = launches;
+  return "";
+}
+
+}  // namespace hc

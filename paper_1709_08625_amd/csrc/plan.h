@@ -1,0 +1,217 @@
+// Host-side plan of the H-matrix assembly and H-Cholesky sweep, plus the POD
+// job descriptors the GPU kernels execute.  Everything here is a function of
+// the two trees only (never of theta), so one plan serves every likelihood
+// evaluation on the same locations; ranks are data dependent and are read by
+// the kernels from a device array of "dynamic dimensions".
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+namespace hc {
+
+// ---------------------------------------------------------------- buffers
+// Every matrix operand is addressed relative to one of these device buffers,
+// so plans do not depend on allocation addresses.
+enum BufId : int32_t {
+  B_DENSE = 0,   // dense leaves (col-major, one tile per dense block)
+  B_U = 1,       // low-rank U factors, p x kcap col-major per block
+  B_V = 2,       // low-rank V factors, q x kcap col-major per block
+  B_SCR = 3,     // per-step scratch (reset every step)
+  B_OMEGA = 4,   // fixed Gaussian test matrix (Nmax x rcap col-major)
+  B_RHS = 5,     // right-hand side solved inside the sweep (cluster order)
+  B_PERS = 6,    // persistent scratch (assembly, R factors, coefficients)
+  B_COUNT = 7
+};
+
+struct Ref {
+  int32_t buf;
+  int32_t ld;
+  int64_t off;  // element offset
+};
+
+// A dimension: static value (slot < 0) or min(dyn[slot] + add, maxv).
+struct Dim {
+  int32_t slot;
+  int32_t add;
+  int32_t maxv;
+};
+inline Dim dim_static(int v) { return Dim{-1, 0, v}; }
+inline Dim dim_dyn(int slot, int maxv, int add = 0) { return Dim{slot, add, maxv}; }
+
+// ---------------------------------------------------------------- GEMM jobs
+// C[i0+i, j0+j] (+)= alpha * sum_kk op(A)[i,kk] * op(B)[kk,j]
+// op(A) is m x k: ta=0 -> A[i + kk*lda], ta=1 -> A[kk + i*lda]
+// op(B) is k x n: tb=0 -> B[kk + j*ldb], tb=1 -> B[j + kk*ldb]
+struct GemmProd {
+  Ref A;
+  Ref B;
+  Dim k;
+  Dim mi;      // rows of C touched by this product (from i0)
+  Dim nj;      // cols of C touched by this product (from j0)
+  int32_t i0, j0;
+  int32_t ta, tb;
+  double alpha;
+};
+
+struct GemmJob {
+  Ref C;
+  Dim m, n;          // extent of C written by this job
+  int32_t zero;      // 1: C := sum (C is overwritten on its m x n extent)
+  int32_t p0, p1;    // products [p0, p1)
+};
+
+// Tile of a GEMM launch (capacity-based grid, dynamic tiles exit early).
+struct GemmTile {
+  int32_t job;
+  int32_t ti, tj;
+  int32_t pad;
+};
+
+// ---------------------------------------------------------------- TSQR jobs
+// R factor of a tall matrix X (rows x cols, cols <= RMAX): the local stage
+// computes one R per segment of consecutive rows; the reduce stage combines
+// the segment Rs of one matrix.  R is stored upper-triangular in an
+// RMAX x RMAX col-major slot (ld = RMAX) and is zero-padded beyond cols.
+struct TsqrSeg {
+  Ref X;          // start of this segment (row offset already applied)
+  int32_t rows;   // rows in this segment
+  Dim cols;
+  Ref R;          // output R of this segment
+};
+struct TsqrRed {
+  Ref R0;         // first segment R (ld RMAX), nseg consecutive slots
+  int32_t nseg;
+  Dim cols;
+  Ref R;          // output
+};
+
+// ---------------------------------------------------------------- small jobs
+enum SmallKind : int32_t {
+  SK_RECOMP = 0,   // SVD(RU RV^T) -> CU = RV^T Y_k, CV = RU^T X_k S_k^-1; rank
+  SK_SKETCH_P = 1, // SVD(RY) -> P = W_y S_y^-1 (kept dirs), kept count
+  SK_SKETCH_F = 2, // Z_k from SVD(RB RQ^-1) -> C = RQ^-1 Z_k; rank
+};
+struct SmallJob {
+  int32_t kind;
+  int32_t out_rank_slot;   // dyn slot receiving the new rank / kept count
+  Dim k;                   // input width (cols of the R factors)
+  Ref R1, R2;              // input R factors (ld RMAX)
+  Ref C1, C2;              // outputs (ld RMAX)
+  int32_t cap;             // maximal allowed output rank
+  Dim sat;                 // sketch width (saturation test); static -1 = none
+  double eps;              // < 0: taken from the launch (-1 eps, -2 tau)
+};
+
+// ---------------------------------------------------------------- leaf jobs
+// Dense leaf target (p, q <= LEAF_MAX): M = D - sum_t U_t V_t^T, written
+// back to D; for diagonal blocks M is then factorised in place (potrf) and
+// sum log L_ii is stored to logdet[leaf].
+struct LeafJob {
+  Ref D;
+  int32_t p, q;
+  int32_t diag;     // 1: potrf
+  int32_t leaf;     // leaf index (diag) for logdet / error reporting
+  int32_t t0, t1;   // terms [t0, t1) in the LeafTerm array
+  int64_t row0;     // global cluster-order index of the first row (errors)
+};
+struct LeafTerm {
+  Ref U;  // rows x k (col-major, ld)
+  Ref V;  // cols x k
+  Dim k;
+  int32_t i0, j0;   // placement inside the target
+  int32_t mi, nj;   // extent
+};
+
+// ---------------------------------------------------------------- trsm jobs
+// X <- L^{-1} X for a panel of right-hand sides, L lower triangular p x p.
+// layout 0: X is p x ncols col-major (ld); layout 1: X^T is stored, i.e.
+// element (i, c) of X is at X[c + i*ld] (dense target solved from the right).
+struct TrsmJob {
+  Ref L;
+  int32_t p;
+  int32_t layout;
+  Ref X;
+  Dim ncols;
+  int32_t c0;       // first column of this job's chunk
+  int32_t cw;       // chunk width
+};
+
+// ---------------------------------------------------------------- stages
+enum StageKind : int32_t { ST_GEMM = 0, ST_TSQR_SEG, ST_TSQR_RED, ST_SMALL, ST_LEAF, ST_TRSM, ST_COPY_RANK };
+struct Stage {
+  int32_t kind;
+  int32_t begin, end;   // item range in the kind's array (tiles for GEMM)
+};
+
+// ---------------------------------------------------------------- tree data
+struct BlockInfo {
+  int32_t level, a, c, kind;   // kind 1 = LR, 0 = dense
+  int64_t r0, r1, c0, c1;      // row/col ranges (cluster order)
+  int64_t off_d;               // dense offset (elements) in B_DENSE
+  int64_t off_u, off_v;        // LR offsets in B_U / B_V
+  int32_t rank_slot;           // dyn slot of the current rank (LR)
+  int32_t rank0_slot;          // dyn slot of the assembly rank (LR)
+};
+
+struct Plan {
+  // structure
+  int64_t n = 0;
+  int D = 0, leaf = 0, kcap = 64, rcap = 74, oversample = 10, rmax = 80;
+  std::vector<std::vector<int64_t>> lo;   // lo[l][i] node start (size 2^l + 1 incl. end)
+  std::vector<BlockInfo> blocks;
+  std::unordered_map<uint64_t, int32_t> status;   // (l,a,c) -> block id, or -1 = subdivided
+  std::vector<int32_t> diag_block;                // leaf j -> block id of (j, j)
+  int64_t dense_elems = 0, u_elems = 0, v_elems = 0;
+  int32_t n_dyn = 0;                               // dynamic dimension slots
+
+  // executable job arrays (all steps share them; stages index into them)
+  std::vector<GemmJob> gjobs;
+  std::vector<GemmProd> gprods;
+  std::vector<GemmTile> gtiles;
+  std::vector<TsqrSeg> tsegs;
+  std::vector<TsqrRed> treds;
+  std::vector<SmallJob> smalls;
+  std::vector<LeafJob> leafs;
+  std::vector<LeafTerm> lterms;
+  std::vector<TrsmJob> trsms;
+
+  // schedules
+  std::vector<Stage> recomp_stages;              // assembly recompression
+  std::vector<std::vector<Stage>> steps;          // factorisation sweep (with fused RHS)
+  std::vector<std::vector<Stage>> steps_nofuse;   // sweep without the RHS
+  int64_t scr_elems = 0;                          // per-step scratch size
+  int64_t pers_elems = 0;                         // persistent scratch size
+  int64_t omega_rows = 0;
+
+  // forward/backward solve schedules on B_RHS (single vector)
+  std::vector<std::vector<Stage>> fsolve_steps;
+  std::vector<std::vector<Stage>> bsolve_steps;
+  // H-matvec C~ x (assembled matrix), x in B_RHS col 0, y in col 1
+  std::vector<Stage> matvec_stages;
+  // y = L~ x (x in B_RHS col 0, y col 1)
+  std::vector<Stage> lmul_stages;
+
+  int64_t rhs_ld = 0;   // leading dimension of B_RHS (= n), 2 columns
+
+  // statistics
+  int64_t n_lr = 0, n_dense = 0, lr_rows = 0;
+  int64_t n_launch_fact = 0;
+};
+
+inline uint64_t key3(int l, int64_t a, int64_t c) {
+  return (uint64_t(l) << 58) | (uint64_t(a) << 29) | uint64_t(c);
+}
+
+// Build the plan from the tree structure.  blocks_lac: n_blocks x 4
+// (level, row node, col node, kind) in breadth-first order.
+// Returns an empty string on success, else an error message.
+std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blocks_lac,
+                       int64_t n_blocks, int kcap, int oversample, bool mixed);
+
+int64_t node_lo(const Plan& P, int l, int64_t i);
+int64_t node_hi(const Plan& P, int l, int64_t i);
+
+}  // namespace hc

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every symbol that include/hcov.h
+declares (CPU only: no compute call needs a GPU here)."""
+import os
+import re
+
+import pytest
+
+from paper_1709_08625_amd import hcov
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"\b(hcov_\w+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_built():
+    assert os.path.exists(hcov.LIB_PATH), "run __graft_entry__.build() first"
+
+
+def test_every_declared_symbol_is_exported():
+    L = hcov.lib()
+    names = declared()
+    assert "hcov_build" in names and "hcov_loglik" in names
+    missing = [s for s in names if not hasattr(L, s)]
+    assert not missing, missing
+
+
+def test_strerror_and_defaults_without_gpu():
+    L = hcov.lib()
+    assert L.hcov_strerror(0) == b"ok"
+    assert L.hcov_strerror(-2) == b"matrix not positive definite"
+    o = hcov.default_opts()
+    assert o.max_rank == 64 and o.precision == hcov.FP64 and abs(o.aca_eps_factor - 0.1) < 1e-15
+
+
+def test_argument_validation_on_host():
+    # invalid arguments are rejected before any device call
+    import numpy as np
+
+    locs = np.random.default_rng(0).random((50, 2))
+    bad = [((1.0, 0.1, 0.5, 1e-4), 0.0, 32, 2.0),      # eps
+           ((1.0, 0.1, 0.5, 1e-4), 1e-8, 1, 2.0),      # leaf
+           ((1.0, 0.1, 0.5, 1e-4), 1e-8, 32, 0.0),     # eta
+           ((-1.0, 0.1, 0.5, 1e-4), 1e-8, 32, 2.0),    # sigma2
+           ((1.0, 0.0, 0.5, 1e-4), 1e-8, 32, 2.0),     # ell
+           ((1.0, 0.1, 0.0, 1e-4), 1e-8, 32, 2.0),     # nu
+           ((1.0, 0.1, 0.5, -1.0), 1e-8, 32, 2.0)]     # nugget
+    for th, eps, leaf, eta in bad:
+        with pytest.raises(hcov.HcovError) as e:
+            hcov.HCov(locs, th, eps=eps, leaf=leaf, eta=eta)
+        assert e.value.code == hcov.EINVAL
+    locs2 = locs.copy()
+    locs2[3, 1] = float("nan")
+    with pytest.raises(hcov.HcovError) as e:
+        hcov.HCov(locs2, (1.0, 0.1, 0.5, 1e-4))
+    assert e.value.code == hcov.EINVAL
