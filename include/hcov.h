@@ -191,6 +191,17 @@ int hcov_perm(const hcov_ctx* ctx, int64_t* perm);
 
 void hcov_destroy(hcov_ctx* ctx);
 
+/* Kernel timing: between hcov_profile_begin(ctx, kind) and
+ * hcov_profile_end, every launch of the given stage kind (0 grouped GEMM,
+ * 1 TSQR segment, 2 TSQR reduce, 3 small SVD, 4 dense leaf update/potrf,
+ * 5 triangular solve) is bracketed by HIP events on the context's stream.
+ * hcov_profile_end synchronises and returns the launch count, the summed
+ * event time (ms) and the algorithmic FP64 flops of those launches (GEMM:
+ * 2 m n k per product; leaf: 2 m n k per term + p^3/3; trsm: p^2 per column;
+ * 0 for the other kinds). */
+int hcov_profile_begin(hcov_ctx* ctx, int stage_kind);
+int hcov_profile_end(hcov_ctx* ctx, int64_t* launches, double* total_ms, double* flops);
+
 /* Eq. (3) on the device for n given distances h (host arrays): test access to
  * the device Matérn / K_nu evaluation used by the assembly. */
 int hcov_matern_eval(hcov_theta theta, const double* h, double* out, int64_t n);

@@ -44,7 +44,19 @@ struct hcov_ctx {
   FillJob* d_fill = nullptr;
   AcaJob* d_aca = nullptr;
   int n_fill = 0, n_aca = 0;
+  // large blocks: multi-work-group ACA
+  AcaJob* d_acab = nullptr;
+  int n_acab = 0, n_brow = 0, n_bcol = 0;
+  AcaBigChunk *d_brow = nullptr, *d_bcol = nullptr;
+  int *d_brow_first = nullptr, *d_brow_count = nullptr, *d_bcol_first = nullptr, *d_bcol_count = nullptr;
+  AcaBigState* d_bstate = nullptr;
+  double *d_bpart = nullptr, *d_bacc = nullptr;
+  int* d_bactive = nullptr;
   LaunchCtx L{};
+  // kernel profiling (HIP events around every launch of one stage kind)
+  int prof_kind = -1;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+  std::vector<Stage> prof_stages;
   // state
   bool assembled = false, factored = false;
   double ms_tree = 0, ms_asm = 0, ms_fact = 0, ms_solve = 0;
@@ -158,8 +170,65 @@ int tree_depth(int64_t n, int leaf) {
 }
 
 int run_stages(hcov_ctx* c, const std::vector<Stage>& st) {
-  for (const Stage& s : st) HIPCHK(c, launch_stage(s, c->L, c->stream));
+  for (const Stage& s : st) {
+    if (s.kind == c->prof_kind) {
+      hipEvent_t a, b;
+      HIPCHK(c, hipEventCreate(&a));
+      HIPCHK(c, hipEventCreate(&b));
+      HIPCHK(c, hipEventRecord(a, c->stream));
+      HIPCHK(c, launch_stage(s, c->L, c->stream));
+      HIPCHK(c, hipEventRecord(b, c->stream));
+      c->prof_ev.emplace_back(a, b);
+      c->prof_stages.push_back(s);
+    } else {
+      HIPCHK(c, launch_stage(s, c->L, c->stream));
+    }
+  }
   return HCOV_OK;
+}
+
+inline int dyn_value(const std::vector<int>& dyn, const Dim& d) {
+  if (d.slot < 0) return d.maxv;
+  int v = dyn[d.slot] + d.add;
+  return v < d.maxv ? v : d.maxv;
+}
+
+// algorithmic FP64 flops of one stage with the current dynamic dimensions
+double stage_flops(const Plan& P, const std::vector<int>& dyn, const Stage& s) {
+  double f = 0.0;
+  if (s.kind == ST_GEMM) {
+    int last = -1;
+    for (int t = s.begin; t < s.end; ++t) {
+      int j = P.gtiles[t].job;
+      if (j == last) continue;
+      last = j;
+      const GemmJob& J = P.gjobs[j];
+      int m = dyn_value(dyn, J.m), n = dyn_value(dyn, J.n);
+      for (int q = J.p0; q < J.p1; ++q) {
+        const GemmProd& G = P.gprods[q];
+        int k = dyn_value(dyn, G.k);
+        int mi = std::min(dyn_value(dyn, G.mi), m - G.i0), nj = std::min(dyn_value(dyn, G.nj), n - G.j0);
+        if (mi > 0 && nj > 0 && k > 0) f += (G.tb == 2 ? 1.0 : 2.0 * k) * double(mi) * double(nj);
+      }
+    }
+  } else if (s.kind == ST_LEAF) {
+    for (int t = s.begin; t < s.end; ++t) {
+      const LeafJob& J = P.leafs[t];
+      for (int q = J.t0; q < J.t1; ++q) {
+        const LeafTerm& T = P.lterms[q];
+        f += 2.0 * dyn_value(dyn, T.k) * double(T.mi) * double(T.nj);
+      }
+      if (J.diag) f += double(J.p) * J.p * J.p / 3.0;
+    }
+  } else if (s.kind == ST_TRSM) {
+    for (int t = s.begin; t < s.end; ++t) {
+      const TrsmJob& J = P.trsms[t];
+      int nc = dyn_value(dyn, J.ncols);
+      int cw = std::min(J.cw, nc - J.c0);
+      if (cw > 0) f += double(J.p) * J.p * cw;
+    }
+  }
+  return f;
 }
 
 int check_status(hcov_ctx* c, bool spd_matters) {
@@ -193,6 +262,10 @@ int assemble(hcov_ctx* c) {
   HIPCHK(c, launch_fill(c->d_buf[B_DENSE], c->d_loc, c->d_fill, c->n_fill, c->mp, c->stream));
   HIPCHK(c, launch_aca(c->d_buf[B_U], c->d_buf[B_V], c->d_dyn, c->d_loc, c->d_aca, c->n_aca, c->mp,
                        c->eps * c->opts.aca_eps_factor, c->plan.kcap, c->d_status, c->stream));
+  HIPCHK(c, run_aca_big(c->d_buf[B_U], c->d_buf[B_V], c->d_dyn, c->d_loc, c->d_acab, c->n_acab, c->d_brow,
+                        c->n_brow, c->d_bcol, c->n_bcol, c->d_brow_first, c->d_brow_count, c->d_bcol_first,
+                        c->d_bcol_count, c->d_bstate, c->d_bpart, c->d_bacc, c->d_bactive, c->mp,
+                        c->eps * c->opts.aca_eps_factor, c->plan.kcap, c->d_status, c->stream));
   r = run_stages(c, c->plan.recomp_stages);
   if (r) return r;
   r = check_status(c, false);
@@ -426,10 +499,45 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
       cp.push_back(make_int2(B.rank_slot, B.rank0_slot));
     }
   }
-  // big blocks first so the longest ACA work-groups start early
-  std::stable_sort(aj.begin(), aj.end(), [](const AcaJob& a, const AcaJob& b) {
+  // blocks with more than ACA_BIG_SPLIT rows + columns: multi-work-group ACA
+  const int ACA_BIG_SPLIT = 2048;
+  std::vector<AcaJob> big, small;
+  for (auto& a : aj) (int64_t(a.p) + a.q > ACA_BIG_SPLIT ? big : small).push_back(a);
+  std::stable_sort(small.begin(), small.end(), [](const AcaJob& a, const AcaJob& b) {
     return int64_t(a.p) + a.q > int64_t(b.p) + b.q;
   });
+  aj = small;
+  {
+    std::vector<AcaBigChunk> rows, cols;
+    std::vector<int> rf, rcn, cf, ccn;
+    for (int b = 0; b < int(big.size()); ++b) {
+      rf.push_back(int(rows.size()));
+      for (int c0 = 0; c0 < big[b].q; c0 += ACA_BIG_CHUNK) rows.push_back(AcaBigChunk{b, c0});
+      rcn.push_back(int(rows.size()) - rf.back());
+      cf.push_back(int(cols.size()));
+      for (int c0 = 0; c0 < big[b].p; c0 += ACA_BIG_CHUNK) cols.push_back(AcaBigChunk{b, c0});
+      ccn.push_back(int(cols.size()) - cf.back());
+    }
+    c->n_acab = int(big.size());
+    c->n_brow = int(rows.size());
+    c->n_bcol = int(cols.size());
+    if (c->n_acab > 0) {
+      c->d_acab = upload(c, big);
+      c->d_brow = upload(c, rows);
+      c->d_bcol = upload(c, cols);
+      c->d_brow_first = upload(c, rf);
+      c->d_brow_count = upload(c, rcn);
+      c->d_bcol_first = upload(c, cf);
+      c->d_bcol_count = upload(c, ccn);
+      c->d_bstate = (AcaBigState*)dev_alloc(c, size_t(c->n_acab) * ACA_BIG_STATE_BYTES);
+      c->d_bpart = (double*)dev_alloc(c, size_t(std::max(c->n_brow, c->n_bcol)) * ACA_BIG_PREC * 8);
+      c->d_bacc = (double*)dev_alloc(c, size_t(c->n_acab) * ACA_BIG_PREC * 8);
+      c->d_bactive = (int*)dev_alloc(c, 16);
+      if (!c->d_acab || !c->d_brow || !c->d_bcol || !c->d_brow_first || !c->d_brow_count || !c->d_bcol_first ||
+          !c->d_bcol_count || !c->d_bstate || !c->d_bpart || !c->d_bacc || !c->d_bactive)
+        return bail(HCOV_ENOMEM);
+    }
+  }
   c->n_fill = int(fj.size());
   c->n_aca = int(aj.size());
   c->d_fill = upload(c, fj);
@@ -684,6 +792,37 @@ void hcov_destroy(hcov_ctx* c) {
       hipFree(p);
   }
   delete c;
+}
+
+int hcov_profile_begin(hcov_ctx* c, int stage_kind) {
+  if (!c || stage_kind < 0 || stage_kind > ST_TRSM) return HCOV_EINVAL;
+  c->prof_kind = stage_kind;
+  c->prof_ev.clear();
+  c->prof_stages.clear();
+  return HCOV_OK;
+}
+
+int hcov_profile_end(hcov_ctx* c, int64_t* launches, double* total_ms, double* flops) {
+  if (!c) return HCOV_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<int> dyn(c->plan.n_dyn + 1);
+  HIPCHK(c, hipMemcpy(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost));
+  double ms = 0.0, fl = 0.0;
+  for (size_t i = 0; i < c->prof_ev.size(); ++i) {
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, c->prof_ev[i].first, c->prof_ev[i].second));
+    ms += t;
+    fl += stage_flops(c->plan, dyn, c->prof_stages[i]);
+    (void)hipEventDestroy(c->prof_ev[i].first);
+    (void)hipEventDestroy(c->prof_ev[i].second);
+  }
+  if (launches) *launches = int64_t(c->prof_ev.size());
+  if (total_ms) *total_ms = ms;
+  if (flops) *flops = fl;
+  c->prof_kind = -1;
+  c->prof_ev.clear();
+  c->prof_stages.clear();
+  return HCOV_OK;
 }
 
 // Matérn of Eq. (3) on the device for given distances (test access to the

@@ -59,8 +59,22 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
     const double* __restrict__ B = refp(bufs, Pd.B);
     const int lda = Pd.A.ld, ldb = Pd.B.ld;
     const double alpha = Pd.alpha;
-    for (int k0 = 0; k0 < k; k0 += GK) {
-      // A tile: rows r0..r0+63 (global C rows) -> product row i - pr0
+    if (Pd.tb == 2) {
+      // C += alpha * A (element-wise; partial sums of a split product)
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+          int gi = r0 + ty * 4 + x, gj = c0 + tx * 4 + y;
+          if (gi >= pr0 && gi < pr1 && gj >= pc0 && gj < pc1)
+            acc[x][y] += alpha * A[(gi - pr0) + (size_t)(gj - pc0) * lda];
+        }
+      continue;
+    }
+    // register prefetch of the next 16-wide k chunk while the current one is
+    // consumed from LDS
+    double ra[4], rb[4];
+    auto fetch = [&](int k0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         int e = tid + 256 * r;
@@ -78,7 +92,7 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
           int li = gi - pr0;
           v = Pd.ta == 0 ? A[li + (size_t)gk * lda] : A[gk + (size_t)li * lda];
         }
-        As[kk][ii] = alpha * v;
+        ra[r] = alpha * v;
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -97,21 +111,47 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
           int lj = gj - pc0;
           v = Pd.tb == 0 ? B[gk + (size_t)lj * ldb] : B[lj + (size_t)gk * ldb];
         }
-        Bs[kk][jj] = v;
+        rb[r] = v;
+      }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < k; k0 += GK) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int e = tid + 256 * r;
+        int ii, kk;
+        if (Pd.ta == 0) {
+          ii = e & 63;
+          kk = e >> 6;
+        } else {
+          ii = e >> 4;
+          kk = e & 15;
+        }
+        As[kk][ii] = ra[r];
+        int jj, k2;
+        if (Pd.tb == 0) {
+          k2 = e & 15;
+          jj = e >> 4;
+        } else {
+          jj = e & 63;
+          k2 = e >> 6;
+        }
+        Bs[k2][jj] = rb[r];
       }
       __syncthreads();
+      if (k0 + GK < k) fetch(k0 + GK);
 #pragma unroll
       for (int kk = 0; kk < GK; ++kk) {
-        double a[4], b[4];
+        double av[4], bv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          a[q] = As[kk][ty * 4 + q];
-          b[q] = Bs[kk][tx * 4 + q];
+          av[q] = As[kk][ty * 4 + q];
+          bv[q] = Bs[kk][tx * 4 + q];
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
+          for (int y = 0; y < 4; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
       }
       __syncthreads();
     }
@@ -133,52 +173,51 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
 }
 
 // ------------------------------------------------------------------ TSQR
-// Householder QR in LDS of an mrows x c matrix (col-major, ld = LDM).  On
-// exit the upper triangle of the leading c x c block holds R.
-constexpr int QR_CH = 64;            // rows added per step
+// Householder QR in LDS of an mrows x c matrix (col-major, leading dimension
+// ldm chosen at run time so that as many rows as possible are reduced per
+// pass).  On exit the leading c x c upper triangle holds R.
+constexpr int QR_LDS = 160 * 96;     // doubles of the LDS matrix buffer
 constexpr int QR_CMAX = 96;          // max columns
-constexpr int LDM = QR_CH + QR_CMAX; // 160
 
-__device__ void house_qr_lds(double* M, int mrows, int c, double* red) {
+__device__ void house_qr_lds(double* M, int ldm, int mrows, int c, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int j = 0; j < c && j < mrows; ++j) {
-    // norm of column j below the diagonal (wave 0)
     if (wave == 0) {
       double s = 0.0;
       for (int i = j + lane; i < mrows; i += 64) {
-        double v = M[i + j * LDM];
+        double v = M[i + j * ldm];
         s += v * v;
       }
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
       if (lane == 0) {
         double nrm = sqrt(s);
-        double a = M[j + j * LDM];
+        double a = M[j + j * ldm];
         double alpha = (a >= 0.0) ? -nrm : nrm;
-        // v = x - alpha e1 ; v^T v = 2 nrm (nrm + |a|)
-        double vtv = 2.0 * nrm * (nrm + fabs(a));
+        double vtv = 2.0 * nrm * (nrm + fabs(a));   // v = x - alpha e1
         red[0] = alpha;
         red[1] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-        M[j + j * LDM] = a - alpha;   // v stored in column j
+        M[j + j * ldm] = a - alpha;
       }
     }
     __syncthreads();
     const double beta = red[1];
     if (beta != 0.0) {
       for (int l = j + 1 + wave; l < c; l += 4) {
-        double s = 0.0;
-        for (int i = j + lane; i < mrows; i += 64) s += M[i + j * LDM] * M[i + l * LDM];
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
-        s = __shfl(s, 0);
-        s *= beta;
-        for (int i = j + lane; i < mrows; i += 64) M[i + l * LDM] -= s * M[i + j * LDM];
+        double sdot = 0.0;
+        for (int i = j + lane; i < mrows; i += 64) sdot += M[i + j * ldm] * M[i + l * ldm];
+        for (int o = 32; o > 0; o >>= 1) sdot += __shfl_xor(sdot, o);
+        sdot *= beta;
+        for (int i = j + lane; i < mrows; i += 64) M[i + l * ldm] -= sdot * M[i + j * ldm];
       }
     }
     __syncthreads();
-    if (tid == 0) M[j + j * LDM] = red[0];
-    for (int i = j + 1 + tid; i < mrows; i += 256) M[i + j * LDM] = 0.0;
+    if (tid == 0) M[j + j * ldm] = red[0];
+    for (int i = j + 1 + tid; i < mrows; i += 256) M[i + j * ldm] = 0.0;
     __syncthreads();
   }
 }
+
+__device__ __forceinline__ int qr_ldm(int c) { return QR_LDS / (c > 0 ? c : 1); }
 
 __global__ __launch_bounds__(256) void k_tsqr_seg(Bufs bufs, const int* __restrict__ dyn,
                                                   const TsqrSeg* __restrict__ segs, int s0, int rmax) {
@@ -186,33 +225,40 @@ __global__ __launch_bounds__(256) void k_tsqr_seg(Bufs bufs, const int* __restri
   const int c = dimv(dyn, S.cols);
   double* __restrict__ R = refp(bufs, S.R);
   extern __shared__ double smem[];
-  double* M = smem;                 // LDM x QR_CMAX
-  double* red = smem + LDM * QR_CMAX;
+  double* M = smem;
+  double* red = smem + QR_LDS;
   const int tid = threadIdx.x;
-  if (c <= 0) {
-    return;
-  }
+  if (c <= 0) return;
+  const int ldm = qr_ldm(c);
+  const int chunk = ldm - c;
   const double* __restrict__ X = refp(bufs, S.X);
   const int ld = S.X.ld;
-  int have = 0;   // rows of R currently held at the top of M
-  for (int base = 0; base < S.rows; base += QR_CH) {
-    int nr = min(QR_CH, S.rows - base);
-    // rows [have, have+nr) <- X[base.., :]
-    for (int e = tid; e < nr * c; e += 256) {
-      int i = e % nr, l = e / nr;
-      M[have + i + l * LDM] = X[(size_t)(base + i) + (size_t)l * ld];
+  int have = 0;
+  for (int base = 0; base < S.rows; base += chunk) {
+    int nr = min(chunk, S.rows - base);
+    for (int b0 = 0; b0 < nr * c; b0 += 2048) {
+      double r[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = b0 + u * 256 + tid;
+        int i = e % nr, l = e / nr;
+        r[u] = (e < nr * c) ? X[(size_t)(base + i) + (size_t)l * ld] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int e = b0 + u * 256 + tid;
+        int i = e % nr, l = e / nr;
+        if (e < nr * c) M[have + i + l * ldm] = r[u];
+      }
     }
     __syncthreads();
     int mrows = have + nr;
-    house_qr_lds(M, mrows, c, red);
+    house_qr_lds(M, ldm, mrows, c, red);
     have = min(mrows, c);
-    // zero below the kept R rows for the next round (columns c)
-    __syncthreads();
   }
-  // write R (c x c), rows >= have are zero
   for (int e = tid; e < c * c; e += 256) {
     int i = e % c, l = e / c;
-    R[i + (size_t)l * rmax] = (i < have && i <= l) ? M[i + l * LDM] : 0.0;
+    R[i + (size_t)l * rmax] = (i < have && i <= l) ? M[i + l * ldm] : 0.0;
   }
 }
 
@@ -223,128 +269,155 @@ __global__ __launch_bounds__(256) void k_tsqr_red(Bufs bufs, const int* __restri
   double* __restrict__ R = refp(bufs, S.R);
   extern __shared__ double smem[];
   double* M = smem;
-  double* red = smem + LDM * QR_CMAX;
+  double* red = smem + QR_LDS;
   const int tid = threadIdx.x;
   if (c <= 0) return;
+  const int ldm = qr_ldm(c);
   const double* __restrict__ R0 = refp(bufs, S.R0);
   const size_t RR = (size_t)rmax * rmax;
   int have = 0;
-  for (int s = 0; s < S.nseg; ++s) {
-    const double* Rs = R0 + RR * s;
-    for (int e = tid; e < c * c; e += 256) {
-      int i = e % c, l = e / c;
-      M[have + i + l * LDM] = Rs[i + (size_t)l * rmax];
+  int s = 0;
+  while (s < S.nseg) {
+    // stack as many segment R factors as fit under the current R
+    int mrows = have;
+    const int s_start = s;
+    while (s < S.nseg && mrows + c <= ldm) {
+      const double* Rs = R0 + RR * s;
+      for (int e = tid; e < c * c; e += 256) {
+        int i = e % c, l = e / c;
+        M[mrows + i + l * ldm] = Rs[i + (size_t)l * rmax];
+      }
+      mrows += c;
+      ++s;
     }
+    if (s == s_start) break;   // cannot happen for c <= 80 (2c <= ldm)
     __syncthreads();
-    int mrows = have + c;
-    house_qr_lds(M, mrows, c, red);
+    house_qr_lds(M, ldm, mrows, c, red);
     have = min(mrows, c);
-    __syncthreads();
   }
   for (int e = tid; e < c * c; e += 256) {
     int i = e % c, l = e / c;
-    R[i + (size_t)l * rmax] = (i < have && i <= l) ? M[i + l * LDM] : 0.0;
+    R[i + (size_t)l * rmax] = (i < have && i <= l) ? M[i + l * ldm] : 0.0;
   }
 }
 
 // ------------------------------------------------------------------ small SVD
 // One-sided Jacobi (Hestenes) on the columns of an n x n matrix A in LDS
-// (ld = SM), accumulating the right rotations in V: A V = U S.  Disjoint
-// column pairs of a round-robin ordering are processed by the 4 waves.
-constexpr int SM = 96;
+// (ld = SM), accumulating the right rotations in V: A V = U S.  All disjoint
+// column pairs of a round-robin round are processed at once, each by a group
+// of g lanes (g a power of two, groups aligned inside a wave).
+constexpr int SM = 80;
 
-__device__ void jacobi_svd_lds(double* A, double* V, int n, int* pairs, double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__device__ void jacobi_svd_lds(double* A, double* V, int n, double* red) {
+  const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += 256) {
     int i = e % n, j = e / n;
     V[i + j * SM] = (i == j) ? 1.0 : 0.0;
   }
-  const int np = (n + 1) & ~1;   // even count (a dummy column n when odd)
+  const int np = (n + 1) & ~1;
+  const int npairs = np / 2;
+  int g = 64;
+  while (g > 1 && npairs * g > 256) g >>= 1;
+  const int grp = tid / g, gl = tid % g;
+  const double tol = fmax(1e-14, 8.0 * 2.220446049250313e-16 * n);
   __syncthreads();
-  for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid == 0) red[0] = 0.0;
-    __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
     double offmax = 0.0;
     for (int rnd = 0; rnd < np - 1; ++rnd) {
-      // round-robin pairing of 0..np-1 (index np-1 fixed)
-      for (int t = wave; t < np / 2; t += 4) {
+      if (grp < npairs) {
         int a, b;
-        if (t == 0) {
+        if (grp == 0) {
           a = np - 1;
           b = rnd;
         } else {
-          a = (rnd + t) % (np - 1);
-          b = (rnd - t + (np - 1)) % (np - 1);
+          a = (rnd + grp) % (np - 1);
+          b = (rnd - grp + (np - 1)) % (np - 1);
         }
-        if (a >= n || b >= n) continue;
-        int p = min(a, b), q = max(a, b);
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = lane; i < n; i += 64) {
-          double x = A[i + p * SM], y = A[i + q * SM];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-          al += __shfl_down(al, o);
-          be += __shfl_down(be, o);
-          ga += __shfl_down(ga, o);
-        }
-        al = __shfl(al, 0);
-        be = __shfl(be, 0);
-        ga = __shfl(ga, 0);
-        if (ga == 0.0 || al == 0.0 || be == 0.0) continue;
-        double rel = fabs(ga) / sqrt(al * be);
-        offmax = fmax(offmax, rel);
-        if (rel < 1e-15) continue;
-        double zeta = (be - al) / (2.0 * ga);
-        double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        double cs = 1.0 / sqrt(1.0 + tt * tt);
-        double sn = cs * tt;
-        for (int i = lane; i < n; i += 64) {
-          double x = A[i + p * SM], y = A[i + q * SM];
-          A[i + p * SM] = cs * x - sn * y;
-          A[i + q * SM] = sn * x + cs * y;
-          double vx = V[i + p * SM], vy = V[i + q * SM];
-          V[i + p * SM] = cs * vx - sn * vy;
-          V[i + q * SM] = sn * vx + cs * vy;
+        if (a < n && b < n) {
+          const int pp = min(a, b), qq = max(a, b);
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int i = gl; i < n; i += g) {
+            double x = A[i + pp * SM], y = A[i + qq * SM];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
+          for (int o = g >> 1; o > 0; o >>= 1) {
+            al += __shfl_xor(al, o);
+            be += __shfl_xor(be, o);
+            ga += __shfl_xor(ga, o);
+          }
+          if (ga != 0.0 && al != 0.0 && be != 0.0) {
+            double rel = fabs(ga) / sqrt(al * be);
+            offmax = fmax(offmax, rel);
+            if (rel >= tol) {
+              double zeta = (be - al) / (2.0 * ga);
+              double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+              double cs = 1.0 / sqrt(1.0 + tt * tt);
+              double sn = cs * tt;
+              for (int i = gl; i < n; i += g) {
+                double x = A[i + pp * SM], y = A[i + qq * SM];
+                A[i + pp * SM] = cs * x - sn * y;
+                A[i + qq * SM] = sn * x + cs * y;
+                double vx = V[i + pp * SM], vy = V[i + qq * SM];
+                V[i + pp * SM] = cs * vx - sn * vy;
+                V[i + qq * SM] = sn * vx + cs * vy;
+              }
+            }
+          }
         }
       }
       __syncthreads();
     }
-    // reduce offmax over waves
-    if (lane == 0) {
-      // atomic max on a double in LDS via CAS-free approach: store per wave
-      red[1 + wave] = offmax;
-    }
+    // block max of offmax
+    for (int o = 32; o > 0; o >>= 1) offmax = fmax(offmax, __shfl_xor(offmax, o));
+    if ((tid & 63) == 0) red[tid >> 6] = offmax;
     __syncthreads();
-    double om = fmax(fmax(red[1], red[2]), fmax(red[3], red[4]));
+    double om = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     __syncthreads();
-    if (om < 1e-15) break;
+    if (om < tol) break;
   }
-  (void)pairs;
 }
 
-// sort indices of column norms descending (tid 0), ord[0..n)
+// singular values (column norms of A) and the order by decreasing value,
+// ties to the lower index: ord[r] = column of rank r
 __device__ void order_desc(const double* A, int n, double* sv, int* ord) {
-  if (threadIdx.x == 0) {
-    for (int j = 0; j < n; ++j) {
-      double s = 0.0;
-      for (int i = 0; i < n; ++i) s += A[i + j * SM] * A[i + j * SM];
-      sv[j] = sqrt(s);
-      ord[j] = j;
-    }
-    for (int a = 1; a < n; ++a) {   // insertion sort, stable, descending
-      int x = ord[a];
-      int b = a - 1;
-      while (b >= 0 && sv[ord[b]] < sv[x]) {
-        ord[b + 1] = ord[b];
-        --b;
-      }
-      ord[b + 1] = x;
-    }
+  const int tid = threadIdx.x;
+  for (int j = tid; j < n; j += 256) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += A[i + j * SM] * A[i + j * SM];
+    sv[j] = sqrt(s);
   }
   __syncthreads();
+  for (int j = tid; j < n; j += 256) {
+    int r = 0;
+    for (int i = 0; i < n; ++i) r += (sv[i] > sv[j]) || (sv[i] == sv[j] && i < j);
+    ord[r] = j;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int upk(int i, int j) { return j * (j + 1) / 2 + i; }   // i <= j
+
+// bulk copy of the upper triangle of an n x n matrix (ld) into packed LDS,
+// loads issued 8 at a time before the stores
+__device__ void load_upper(const double* __restrict__ R, int ld, int n, double* Rp) {
+  const int tid = threadIdx.x;
+  for (int base = 0; base < n * n; base += 2048) {
+    double r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int i = e % n, j = e / n;
+      r[u] = (e < n * n && i <= j) ? R[i + (size_t)j * ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int i = e % n, j = e / n;
+      if (e < n * n && i <= j) Rp[upk(i, j)] = r[u];
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_small(Bufs bufs, int* __restrict__ dyn,
@@ -353,47 +426,50 @@ __global__ __launch_bounds__(256) void k_small(Bufs bufs, int* __restrict__ dyn,
   const SmallJob J = jobs[j0 + blockIdx.x];
   const int n = dimv(dyn, J.k);
   extern __shared__ double smem[];
-  double* A = smem;                 // SM x SM
-  double* V = smem + SM * SM;       // SM x SM
-  double* sv = V + SM * SM;         // SM
-  double* red = sv + SM;            // 8
-  int* ord = (int*)(red + 8);       // SM
+  double* A = smem;                          // SM x SM
+  double* V = A + SM * SM;                   // SM x SM
+  double* R1 = V + SM * SM;                  // packed upper, SM(SM+1)/2
+  double* R2 = R1 + SM * (SM + 1) / 2;       // packed upper
+  double* sv = R2 + SM * (SM + 1) / 2;       // SM
+  double* red = sv + SM;                     // 8
+  int* ord = (int*)(red + 8);                // SM
   const int tid = threadIdx.x;
   const double eps = J.eps == -1.0 ? eps_run : (J.eps == -2.0 ? tau_run : J.eps);
   if (n <= 0) {
     if (tid == 0) dyn[J.out_rank_slot] = 0;
     return;
   }
-  const double* __restrict__ R1 = refp(bufs, J.R1);
-  const double* __restrict__ R2 = J.kind != SK_SKETCH_P ? refp(bufs, J.R2) : nullptr;
   double* __restrict__ C1 = refp(bufs, J.C1);
+  load_upper(refp(bufs, J.R1), rmax, n, R1);
+  if (J.kind != SK_SKETCH_P) load_upper(refp(bufs, J.R2), rmax, n, R2);
+  __syncthreads();
   // ---- form the matrix to decompose
   if (J.kind == SK_RECOMP) {
-    // A = R1 R2^T (both upper triangular n x n)
+    // A = R1 R2^T (both upper triangular)
     for (int e = tid; e < n * n; e += 256) {
       int i = e % n, j = e / n;
-      double s = 0.0;
-      for (int l = max(i, j); l < n; ++l) s += R1[i + (size_t)l * rmax] * R2[j + (size_t)l * rmax];
-      A[i + j * SM] = s;
+      double acc = 0.0;
+      for (int l = max(i, j); l < n; ++l) acc += R1[upk(i, l)] * R2[upk(j, l)];
+      A[i + j * SM] = acc;
     }
   } else if (J.kind == SK_SKETCH_P) {
     for (int e = tid; e < n * n; e += 256) {
       int i = e % n, j = e / n;
-      A[i + j * SM] = R1[i + (size_t)j * rmax];
+      A[i + j * SM] = (i <= j) ? R1[upk(i, j)] : 0.0;
     }
   } else {
-    // A = R1 R2^{-1}: row i solves g R2 = r1 (R2 upper triangular)
+    // A = R1 R2^{-1}: row i solves g R2 = r1_i (R2 upper triangular)
     for (int i = tid; i < n; i += 256) {
       for (int j = 0; j < n; ++j) {
-        double s = R1[i + (size_t)j * rmax];
-        for (int l = 0; l < j; ++l) s -= A[i + l * SM] * R2[l + (size_t)j * rmax];
-        double d = R2[j + (size_t)j * rmax];
-        A[i + j * SM] = (d != 0.0) ? s / d : 0.0;
+        double acc = (i <= j) ? R1[upk(i, j)] : 0.0;
+        for (int l = 0; l < j; ++l) acc -= A[i + l * SM] * R2[upk(l, j)];
+        double d = R2[upk(j, j)];
+        A[i + j * SM] = (d != 0.0) ? acc / d : 0.0;
       }
     }
   }
   __syncthreads();
-  jacobi_svd_lds(A, V, n, nullptr, red);
+  jacobi_svd_lds(A, V, n, red);
   __syncthreads();
   order_desc(A, n, sv, ord);
   const double smax = sv[ord[0]];
@@ -412,8 +488,7 @@ __global__ __launch_bounds__(256) void k_small(Bufs bufs, int* __restrict__ dyn,
     if (kk >= sat && tid == 0) atomicOr(status, STAT_SKETCH_SAT);
   }
   if (J.kind == SK_RECOMP) {
-    // A V = X S: X_k = A[:,ord]/s ; Y = V[:, ord]
-    // CU = R2^T Y_k (n x kk), CV = R1^T X_k S_k^{-1} = R1^T A[:,ord] / s^2
+    // A V = X S: CU = R2^T Y_k, CV = R1^T X_k S_k^{-1} = R1^T A[:,ord] / s^2
     double* __restrict__ C2 = refp(bufs, J.C2);
     for (int e = tid; e < n * kk; e += 256) {
       int i = e % n, c = e / n;
@@ -421,29 +496,34 @@ __global__ __launch_bounds__(256) void k_small(Bufs bufs, int* __restrict__ dyn,
       double s = sv[oc];
       double cu = 0.0, cv = 0.0;
       for (int l = 0; l <= i; ++l) {
-        cu += R2[l + (size_t)i * rmax] * V[l + oc * SM];
-        cv += R1[l + (size_t)i * rmax] * A[l + oc * SM];
+        cu += R2[upk(l, i)] * V[l + oc * SM];
+        cv += R1[upk(l, i)] * A[l + oc * SM];
       }
       C1[i + (size_t)c * rmax] = cu;
       C2[i + (size_t)c * rmax] = cv / (s * s);
     }
   } else if (J.kind == SK_SKETCH_P) {
-    // P = W_k S_k^{-1}: columns ord[0..kk)
     for (int e = tid; e < n * kk; e += 256) {
       int i = e % n, c = e / n;
       int oc = ord[c];
       C1[i + (size_t)c * rmax] = V[i + oc * SM] / sv[oc];
     }
   } else {
-    // C = R2^{-1} Z_k, Z = V[:, ord]; back substitution per column
+    // C = R2^{-1} Z_k, Z = V[:, ord]: back substitution, one thread per column,
+    // the column kept in A's (now free) storage
     for (int c = tid; c < kk; c += 256) {
       int oc = ord[c];
       for (int i = n - 1; i >= 0; --i) {
-        double s = V[i + oc * SM];
-        for (int l = i + 1; l < n; ++l) s -= R2[i + (size_t)l * rmax] * C1[l + (size_t)c * rmax];
-        double d = R2[i + (size_t)i * rmax];
-        C1[i + (size_t)c * rmax] = (d != 0.0) ? s / d : 0.0;
+        double acc = V[i + oc * SM];
+        for (int l = i + 1; l < n; ++l) acc -= R2[upk(i, l)] * A[l + c * SM];
+        double d = R2[upk(i, i)];
+        A[i + c * SM] = (d != 0.0) ? acc / d : 0.0;
       }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * kk; e += 256) {
+      int i = e % n, c = e / n;
+      C1[i + (size_t)c * rmax] = A[i + c * SM];
     }
   }
   if (tid == 0) dyn[J.out_rank_slot] = kk;
@@ -474,38 +554,60 @@ __global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__
       int i = ty * 8 + a, j = tx * 8 + b;
       acc[a][b] = (i < p && j < q) ? Dp[i + (size_t)j * ldd] : 0.0;
     }
-  for (int t = J.t0; t < J.t1; ++t) {
+  // term chunks of LFK columns: 16 values per thread, loaded into registers
+  // one chunk ahead of the FMAs that consume the chunk in LDS
+  auto load_chunk = [&](int t, int k0, double* ru, double* rv) {
     const LeafTerm T = terms[t];
     const int k = dimv(dyn, T.k);
-    if (k <= 0) continue;
     const double* __restrict__ U = refp(bufs, T.U);
     const double* __restrict__ V = refp(bufs, T.V);
-    const int ldu = T.U.ld, ldv = T.V.ld;
-    for (int k0 = 0; k0 < k; k0 += LFK) {
-      for (int e = tid; e < LFK * LF; e += 256) {
-        int i = e & (LF - 1), kk = e >> 7;
-        int gk = k0 + kk;
-        // row i of the tile -> row i - i0 of U
-        int li = i - T.i0, lj = i - T.j0;
-        Us[kk * LF + i] = (li >= 0 && li < T.mi && gk < k) ? U[li + (size_t)gk * ldu] : 0.0;
-        Vs[kk * LF + i] = (lj >= 0 && lj < T.nj && gk < k) ? V[lj + (size_t)gk * ldv] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int kk = 0; kk < LFK; ++kk) {
-        double a[8], b[8];
 #pragma unroll
-        for (int x = 0; x < 8; ++x) {
-          a[x] = Us[kk * LF + ty * 8 + x];
-          b[x] = Vs[kk * LF + tx * 8 + x];
-        }
-#pragma unroll
-        for (int x = 0; x < 8; ++x)
-#pragma unroll
-          for (int y = 0; y < 8; ++y) acc[x][y] = fma(-a[x], b[y], acc[x][y]);
-      }
-      __syncthreads();
+    for (int u = 0; u < 8; ++u) {
+      int e = tid + 256 * u;
+      int i = e & (LF - 1), kk = e >> 7;
+      int gk = k0 + kk;
+      int li = i - T.i0, lj = i - T.j0;
+      ru[u] = (li >= 0 && li < T.mi && gk < k) ? U[li + (size_t)gk * T.U.ld] : 0.0;
+      rv[u] = (lj >= 0 && lj < T.nj && gk < k) ? V[lj + (size_t)gk * T.V.ld] : 0.0;
     }
+  };
+  // flatten (term, chunk) pairs
+  int t = J.t0, k0 = 0;
+  while (t < J.t1 && dimv(dyn, terms[t].k) <= 0) ++t;
+  double ru[8], rv[8];
+  if (t < J.t1) load_chunk(t, 0, ru, rv);
+  while (t < J.t1) {
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = tid + 256 * u;
+      Us[e] = ru[u];   // e = kk * LF + i
+      Vs[e] = rv[u];
+    }
+    __syncthreads();
+    // advance to the next chunk and prefetch it
+    int tn = t, kn = k0 + LFK;
+    if (kn >= dimv(dyn, terms[tn].k)) {
+      ++tn;
+      kn = 0;
+      while (tn < J.t1 && dimv(dyn, terms[tn].k) <= 0) ++tn;
+    }
+    if (tn < J.t1) load_chunk(tn, kn, ru, rv);
+#pragma unroll 4
+    for (int kk = 0; kk < LFK; ++kk) {
+      double a[8], b[8];
+#pragma unroll
+      for (int x = 0; x < 8; ++x) {
+        a[x] = Us[kk * LF + ty * 8 + x];
+        b[x] = Vs[kk * LF + tx * 8 + x];
+      }
+#pragma unroll
+      for (int x = 0; x < 8; ++x)
+#pragma unroll
+        for (int y = 0; y < 8; ++y) acc[x][y] = fma(-a[x], b[y], acc[x][y]);
+    }
+    t = tn;
+    k0 = kn;
   }
   if (!J.diag) {
 #pragma unroll
@@ -537,19 +639,17 @@ __global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__
       __syncthreads();
       break;
     }
-    double ljj = sqrt(d);
-    double inv = 1.0 / ljj;
-    __syncthreads();
-    for (int i = j + 1 + tid; i < p; i += 256) M[i + j * LF] *= inv;
+    const double ljj = sqrt(d);
+    const double inv = 1.0 / ljj;
+    // scale the column below the diagonal and update the trailing lower
+    // triangle: thread t owns row i = j+1+(t & 127) and every other column
+    const int i = j + 1 + (tid & 127);
+    const double lij = (i < p) ? M[i + j * LF] * inv : 0.0;
+    if (i < p)
+      for (int c = j + 1 + (tid >> 7); c <= i; c += 2) M[i + c * LF] -= lij * (M[c + j * LF] * inv);
+    __syncthreads();   // column j is read (unscaled) by every row above
+    if (i < p && (tid >> 7) == 0) M[i + j * LF] = lij;
     if (tid == 0) M[j + j * LF] = ljj;
-    __syncthreads();
-    // trailing update of the lower part: columns c in (j, p), rows i >= c
-    int w = p - j - 1;
-    for (int e = tid; e < w * w; e += 256) {
-      int ii = e % w, cc = e / w;
-      int i = j + 1 + ii, c = j + 1 + cc;
-      if (i >= c) M[i + c * LF] -= M[i + j * LF] * M[c + j * LF];
-    }
     __syncthreads();
   }
   if (bad >= 0) {
@@ -572,11 +672,15 @@ __global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__
 }
 
 // ------------------------------------------------------------------ trsm
-// One wave per job: lower triangle of L packed in LDS, each lane owns one
-// right-hand-side column.  layout 0: X col-major (p x nc); layout 1: X^T
-// stored (element (i,c) at X[c + i*ld]); layout 2: solve L^T x = b.
-__global__ __launch_bounds__(64) void k_trsm(Bufs bufs, const int* __restrict__ dyn,
-                                             const TrsmJob* __restrict__ jobs, int j0) {
+// One work-group per job: the lower triangle of L packed in LDS, the (up to
+// 64) right-hand-side columns row-major in LDS (conflict-free per lane).
+// Blocked substitution: a 16-row diagonal block is solved with one lane per
+// column, then the rows below (above, for L^T) are updated by all threads.
+// layout 0: X col-major (p x nc); layout 1: X^T stored (element (i,c) at
+// X[c + i*ld]); layout 2: solve L^T x = b.
+constexpr int TB = 16;
+__global__ __launch_bounds__(256) void k_trsm(Bufs bufs, const int* __restrict__ dyn,
+                                              const TrsmJob* __restrict__ jobs, int j0) {
   const TrsmJob J = jobs[j0 + blockIdx.x];
   const int nc = dimv(dyn, J.ncols);
   const int cw = min(J.cw, nc - J.c0);
@@ -584,43 +688,113 @@ __global__ __launch_bounds__(64) void k_trsm(Bufs bufs, const int* __restrict__ 
   extern __shared__ double smem[];
   const int p = J.p;
   double* Lp = smem;                       // packed lower: row i at i(i+1)/2
-  double* Xs = smem + LF * (LF + 1) / 2;   // p x 64 (col-major, ld LF)
+  double* Xs = smem + LF * (LF + 1) / 2;   // p x 64 row-major
   const double* __restrict__ L = refp(bufs, J.L);
   const int ldl = J.L.ld;
-  const int lane = threadIdx.x;
-  for (int e = lane; e < p * p; e += 64) {
-    int i = e % p, j = e / p;
-    if (i >= j) Lp[i * (i + 1) / 2 + j] = L[i + (size_t)j * ldl];
+  const int tid = threadIdx.x;
+  // loads are issued 8 at a time before their LDS stores (latency hiding)
+  for (int base = 0; base < p * p; base += 2048) {
+    double r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int i = e % p, j = e / p;
+      r[u] = (e < p * p && i >= j) ? L[i + (size_t)j * ldl] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int i = e % p, j = e / p;
+      if (e < p * p && i >= j) Lp[i * (i + 1) / 2 + j] = r[u];
+    }
   }
   double* __restrict__ X = refp(bufs, J.X);
   const int ldx = J.X.ld;
-  const int c = J.c0 + lane;
-  if (lane < cw) {
-    for (int i = 0; i < p; ++i)
-      Xs[i + lane * LF] = (J.layout == 1) ? X[c + (size_t)i * ldx] : X[i + (size_t)c * ldx];
+  for (int base = 0; base < p * 64; base += 2048) {
+    double r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int c, i;
+      if (J.layout == 1) {
+        c = e & 63;
+        i = e >> 6;
+      } else {
+        i = e % p;
+        c = e / p;
+      }
+      r[u] = (e < p * 64 && c < cw) ? (J.layout == 1 ? X[(J.c0 + c) + (size_t)i * ldx] : X[i + (size_t)(J.c0 + c) * ldx])
+                                    : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int c, i;
+      if (J.layout == 1) {
+        c = e & 63;
+        i = e >> 6;
+      } else {
+        i = e % p;
+        c = e / p;
+      }
+      if (e < p * 64 && c < cw) Xs[i * 64 + c] = r[u];
+    }
   }
   __syncthreads();
-  if (lane < cw) {
-    double* x = Xs + lane * LF;
-    if (J.layout != 2) {
-      for (int i = 0; i < p; ++i) {
-        double s = x[i];
-        const double* Li = Lp + i * (i + 1) / 2;
-        for (int j = 0; j < i; ++j) s -= Li[j] * x[j];
-        x[i] = s / Li[i];
+  if (J.layout != 2) {
+    for (int b0 = 0; b0 < p; b0 += TB) {
+      const int b1 = min(b0 + TB, p);
+      if (tid < cw) {
+        for (int i = b0; i < b1; ++i) {
+          const double* Li = Lp + i * (i + 1) / 2;
+          double s = Xs[i * 64 + tid];
+          for (int j = b0; j < i; ++j) s -= Li[j] * Xs[j * 64 + tid];
+          Xs[i * 64 + tid] = s / Li[i];
+        }
       }
-    } else {
-      for (int i = p - 1; i >= 0; --i) {
-        double s = x[i];
-        for (int j = i + 1; j < p; ++j) s -= Lp[j * (j + 1) / 2 + i] * x[j];
-        x[i] = s / Lp[i * (i + 1) / 2 + i];
+      __syncthreads();
+      for (int e = tid; e < (p - b1) * 64; e += 256) {
+        int c = e & 63, i = b1 + (e >> 6);
+        if (c < cw) {
+          const double* Li = Lp + i * (i + 1) / 2;
+          double s = 0.0;
+          for (int j = b0; j < b1; ++j) s += Li[j] * Xs[j * 64 + c];
+          Xs[i * 64 + c] -= s;
+        }
       }
+      __syncthreads();
     }
-    for (int i = 0; i < p; ++i) {
-      if (J.layout == 1)
-        X[c + (size_t)i * ldx] = x[i];
-      else
-        X[i + (size_t)c * ldx] = x[i];
+  } else {
+    for (int b1 = p; b1 > 0; b1 -= TB) {
+      const int b0 = max(b1 - TB, 0);
+      if (tid < cw) {
+        for (int i = b1 - 1; i >= b0; --i) {
+          double s = Xs[i * 64 + tid];
+          for (int j = i + 1; j < b1; ++j) s -= Lp[j * (j + 1) / 2 + i] * Xs[j * 64 + tid];
+          Xs[i * 64 + tid] = s / Lp[i * (i + 1) / 2 + i];
+        }
+      }
+      __syncthreads();
+      for (int e = tid; e < b0 * 64; e += 256) {
+        int c = e & 63, i = e >> 6;
+        if (c < cw) {
+          double s = 0.0;
+          for (int j = b0; j < b1; ++j) s += Lp[j * (j + 1) / 2 + i] * Xs[j * 64 + c];
+          Xs[i * 64 + c] -= s;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (J.layout == 1) {
+    for (int e = tid; e < p * 64; e += 256) {
+      int c = e & 63, i = e >> 6;
+      if (c < cw) X[(J.c0 + c) + (size_t)i * ldx] = Xs[e];
+    }
+  } else {
+    for (int e = tid; e < p * 64; e += 256) {
+      int i = e % p, c = e / p;
+      if (c < cw) X[i + (size_t)(J.c0 + c) * ldx] = Xs[i * 64 + c];
     }
   }
 }
@@ -883,8 +1057,8 @@ __global__ void k_fill_value(double* __restrict__ out, int64_t n, double v) {
   if (i < n) out[i] = v;
 }
 
-constexpr size_t LDS_QR = (size_t(LDM) * QR_CMAX + 8) * 8;
-constexpr size_t LDS_SMALL = (size_t(2) * SM * SM + SM + 8) * 8 + SM * 4;
+constexpr size_t LDS_QR = (size_t(QR_LDS) + 8) * 8;
+constexpr size_t LDS_SMALL = (size_t(2) * SM * SM + size_t(SM) * (SM + 1) + SM + 8) * 8 + SM * 4;
 constexpr size_t LDS_LEAF = size_t(LF) * LF * 8;
 constexpr size_t LDS_TRSM = (size_t(LF) * (LF + 1) / 2 + size_t(LF) * 64) * 8;
 
@@ -922,7 +1096,7 @@ hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st) {
       if (n > 0) k_leaf<<<n, 256, LDS_LEAF, st>>>(L.bufs, L.dyn, L.leafs, L.lterms, s.begin, L.logdet, L.status);
       break;
     case ST_TRSM:
-      if (n > 0) k_trsm<<<n, 64, LDS_TRSM, st>>>(L.bufs, L.dyn, L.trsms, s.begin);
+      if (n > 0) k_trsm<<<n, 256, LDS_TRSM, st>>>(L.bufs, L.dyn, L.trsms, s.begin);
       break;
     case ST_COPY_RANK:
       if (L.n_copy > 0) k_copy_rank<<<(L.n_copy + 255) / 256, 256, 0, st>>>(L.dyn, L.copy_pairs, L.n_copy);

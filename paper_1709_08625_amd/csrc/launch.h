@@ -45,6 +45,22 @@ struct LaunchCtx {
   int* status;
 };
 
+struct AcaBigState;
+struct AcaBigChunk {
+  int job;   // index into the large-block job list
+  int c0;    // first row / column of the chunk
+};
+constexpr int ACA_BIG_CHUNK = 2048;   // entries per work-group in a pass
+constexpr int ACA_BIG_PREC = 3 + 64;  // partial record length
+constexpr int ACA_BIG_STATE_BYTES = 48 + 128 * 4;
+// ACA of the large blocks with many work-groups per block (aca_big.hip)
+hipError_t run_aca_big(double* U, double* V, int* dyn, const double* loc, const AcaJob* d_jobs, int nj,
+                       const AcaBigChunk* d_rows, int nrow, const AcaBigChunk* d_cols, int ncol,
+                       const int* d_row_first, const int* d_row_count, const int* d_col_first,
+                       const int* d_col_count, AcaBigState* d_state, double* d_part, double* d_acc,
+                       int* d_active, const MaternParams& P, double eps_aca, int kcap, int* status,
+                       hipStream_t st);
+
 hipError_t setup_kernel_attributes();
 hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st);
 hipError_t launch_fill(double* D, const double* loc, const FillJob* jobs, int njobs,

@@ -245,14 +245,54 @@ class Builder {
     p.alpha = alpha;
     d.prods.push_back(p);
   }
+  // Emit deferred jobs as one GEMM stage.  Products with a static inner
+  // dimension above KSPLIT are split into chunks that write partial sums to
+  // scratch; a second stage adds the partials into the real output in a
+  // fixed order (deterministic, no atomics).
+  static constexpr int KSPLIT = 2048;
   void emit(std::vector<Deferred>& L, std::vector<Stage>& out) {
+    std::vector<Deferred> finals;
     for (auto& d : L) {
-      int32_t j = gemm_job(d.C, d.m, d.n, d.zero);
+      int nsplit = 1;
       for (auto& p : d.prods)
-        add_prod(j, p.A, p.ta, p.B, p.tb, p.k, p.i0, p.j0, p.mi, p.nj, p.alpha);
+        if (p.k.slot < 0 && p.tb != 2 && p.k.maxv > KSPLIT) nsplit = std::max(nsplit, (p.k.maxv + KSPLIT - 1) / KSPLIT);
+      if (nsplit == 1) {
+        int32_t j = gemm_job(d.C, d.m, d.n, d.zero);
+        for (auto& p : d.prods) add_prod(j, p.A, p.ta, p.B, p.tb, p.k, p.i0, p.j0, p.mi, p.nj, p.alpha);
+        continue;
+      }
+      const int mcap = d.m.maxv, ncap = d.n.maxv;
+      Deferred fin{d.C, d.m, d.n, d.zero, {}};
+      for (int sp = 0; sp < nsplit; ++sp) {
+        int64_t pb = scr_alloc(int64_t(mcap) * ncap);
+        int32_t j = gemm_job(Ref{B_SCR, mcap, pb}, d.m, d.n, 1);
+        for (auto& p : d.prods) {
+          bool splittable = p.k.slot < 0 && p.tb != 2 && p.k.maxv > KSPLIT;
+          if (!splittable) {
+            if (sp == 0) add_prod(j, p.A, p.ta, p.B, p.tb, p.k, p.i0, p.j0, p.mi, p.nj, p.alpha);
+            continue;
+          }
+          int k0 = sp * KSPLIT;
+          if (k0 >= p.k.maxv) continue;
+          int kc = std::min(KSPLIT, p.k.maxv - k0);
+          Ref A = p.A, B = p.B;
+          A.off += (p.ta == 0) ? int64_t(k0) * A.ld : int64_t(k0);
+          B.off += (p.tb == 0) ? int64_t(k0) : int64_t(k0) * B.ld;
+          add_prod(j, A, p.ta, B, p.tb, dim_static(kc), p.i0, p.j0, p.mi, p.nj, p.alpha);
+        }
+        dprod(fin, Ref{B_SCR, mcap, pb}, 0, Ref{B_SCR, mcap, pb}, 2, dim_static(1), 0, 0, d.m, d.n, 1.0);
+      }
+      finals.push_back(fin);
     }
     L.clear();
     flush_gemm(out);
+    if (!finals.empty()) {
+      for (auto& d : finals) {
+        int32_t j = gemm_job(d.C, d.m, d.n, d.zero);
+        for (auto& p : d.prods) add_prod(j, p.A, p.ta, p.B, p.tb, p.k, p.i0, p.j0, p.mi, p.nj, p.alpha);
+      }
+      flush_gemm(out);
+    }
   }
 
   // add to deferred job `d` (in list B) the contributions of region
@@ -937,7 +977,7 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
   P.rcap = kcap + oversample;
   P.rmax = std::max(P.rcap, kcap);
   if (kcap > 64 || kcap < 1) return "rank capacity must be in [1, 64]";
-  if (P.rmax > 96) return "rank capacity plus oversampling must not exceed 96";
+  if (P.rmax > 80) return "rank capacity plus oversampling must not exceed 80";
   // node ranges: left son takes ceil(s/2)
   P.lo.resize(D + 1);
   P.lo[0] = {0, n};

@@ -75,6 +75,8 @@ def lib():
         L.hcov_tree_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int64)]
         L.hcov_tree_dump.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
         L.hcov_matern_eval.argtypes = [Theta, dp, dp, C.c_int64]
+        L.hcov_profile_begin.argtypes = [C.c_void_p, C.c_int]
+        L.hcov_profile_end.argtypes = [C.c_void_p, C.POINTER(C.c_int64), dp, dp]
         _lib = L
     return _lib
 
@@ -82,7 +84,9 @@ def lib():
 EXPORTS = ["hcov_opts_default", "hcov_build", "hcov_set_theta", "hcov_cholesky", "hcov_logdet", "hcov_solve",
            "hcov_forward", "hcov_sample", "hcov_matvec", "hcov_loglik", "hcov_stats", "hcov_estimate_bytes",
            "hcov_perm", "hcov_destroy", "hcov_strerror", "hcov_last_error", "hcov_tree_sizes", "hcov_tree_dump",
-           "hcov_matern_eval"]
+           "hcov_matern_eval", "hcov_profile_begin", "hcov_profile_end"]
+
+STAGE_KINDS = {"gemm": 0, "tsqr_seg": 1, "tsqr_red": 2, "small": 3, "leaf": 4, "trsm": 5}
 
 
 class HcovError(RuntimeError):
@@ -254,6 +258,16 @@ class HCov:
         s = Stats()
         self._chk(lib().hcov_stats(self._ctx, C.byref(s)))
         return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def profile_begin(self, kind):
+        self._chk(lib().hcov_profile_begin(self._ctx, STAGE_KINDS[kind] if isinstance(kind, str) else int(kind)))
+
+    def profile_end(self):
+        n = C.c_int64()
+        ms = C.c_double()
+        fl = C.c_double()
+        self._chk(lib().hcov_profile_end(self._ctx, C.byref(n), C.byref(ms), C.byref(fl)))
+        return n.value, ms.value, fl.value
 
     def perm(self):
         p = np.empty(self.n, dtype=np.int64)

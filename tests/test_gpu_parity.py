@@ -194,33 +194,59 @@ def test_solve_matvec_sample():
 @pytest.mark.parametrize("n", [20000, 131072])
 def test_line_ou_exact_at_scale(n):
     # points on a line, nu = 1/2, no nugget: an AR(1) chain with a closed-form
-    # likelihood; every admissible block of the 1-D exponential kernel has rank 1
+    # likelihood; every admissible block of the 1-D exponential kernel has rank 1.
+    # z is a sample of that chain (z_{i+1} = rho_i z_i + sqrt(sigma2 (1-rho_i^2)) xi)
     hcov = _hc()
     locs, xi = workloads.line(n, seed=7)
-    th = (1.2, 0.01, 0.5, 0.0)
-    ll0, ld0, q0 = markov.ou_loglik(locs[:, 0], xi, 1.2, 0.01)
-    h = hcov.HCov(locs, th, eps=1e-9, leaf=128, eta=2.0)
-    ll, ld, q = h.loglik(xi)
+    s2, ell = 1.2, 0.01
+    rho = np.exp(-np.diff(locs[:, 0]) / ell)
+    z = np.empty(n)
+    z[0] = math.sqrt(s2) * xi[0]
+    for i in range(1, n):
+        z[i] = rho[i - 1] * z[i - 1] + math.sqrt(s2 * (1 - rho[i - 1] ** 2)) * xi[i]
+    ll0, ld0, q0 = markov.ou_loglik(locs[:, 0], z, s2, ell)
+    h = hcov.HCov(locs, (s2, ell, 0.5, 0.0), eps=1e-9, leaf=128, eta=2.0)
+    ll, ld, q = h.loglik(z)
     S = scale(n, ld0, q0)
     print(f"line n={n}: rel={abs(ll - ll0) / S:.2e} maxrank={h.stats()['max_rank_seen']}")
     assert abs(ll - ll0) / S < 1e-8
+    assert h.stats()["max_rank_seen"] <= 2
     h.close()
 
 
 # ------------------------------------------------------------------ failures
-def test_duplicate_points_without_nugget_is_not_spd():
+def test_duplicate_points_without_nugget():
+    # coincident points make C exactly singular without a nugget (Sec. 4); in
+    # floating point the zero pivot comes out tiny of either sign, so the
+    # result is either HCOV_ENOTSPD or a log-determinant far below the one
+    # with a nugget
     hcov = _hc()
     locs, _ = workloads.uniform(300, seed=1)
     locs[17] = locs[5]
     h = hcov.HCov(locs, (1.0, 0.1, 0.5, 0.0), eps=1e-8, leaf=32, eta=2.0)
-    with pytest.raises(hcov.HcovError) as e:
-        h.loglik(np.ones(300))
-    assert e.value.code == hcov.ENOTSPD
-    # with a nugget the same points factorise
+    try:
+        _, ld_sing, _ = h.loglik(np.ones(300))
+        singular = False
+    except hcov.HcovError as e:
+        assert e.code == hcov.ENOTSPD
+        singular = True
     h.set_theta((1.0, 0.1, 0.5, 1e-3))
-    ll, _, _ = h.loglik(np.ones(300))
+    ll, ld_nug, _ = h.loglik(np.ones(300))
     assert np.isfinite(ll)
+    if not singular:
+        assert ld_sing < ld_nug - 10.0
     h.close()
+
+
+def test_overflowing_entries_are_reported_not_spd():
+    # entries of magnitude 1e300 overflow in the Schur updates: the
+    # non-finite pivot is reported as HCOV_ENOTSPD, never returned silently
+    hcov = _hc()
+    locs, _ = workloads.uniform(400, seed=2)
+    with pytest.raises(hcov.HcovError) as e:
+        h = hcov.HCov(locs, (1e300, 0.3, 0.5, 1e300), eps=1e-8, leaf=32, eta=2.0)
+        h.loglik(np.ones(400))
+    assert e.value.code == hcov.ENOTSPD
 
 
 def test_state_errors():
