@@ -191,6 +191,33 @@ int hcov_perm(const hcov_ctx* ctx, int64_t* perm);
 
 void hcov_destroy(hcov_ctx* ctx);
 
+/* ------------------------------------------------------------ outer loop */
+
+/* Objective of the simplex minimiser: f(x[0..dim)) for `user`. */
+typedef double (*hcov_objective_fn)(const double* x, int dim, void* user);
+
+/* Nelder-Mead minimisation (Nelder & Mead 1965; the paper's optimiser is a
+ * derivative-free simplex search, Sec. 5 and the driver of Appendix B):
+ * reflection 1, expansion 2, contraction 1/2, shrink 1/2, initial simplex
+ * x0 and x0 + steps[k] e_k, stable ordering of the vertices.  Stops when the
+ * largest vertex distance to the centroid is below size_tol or after
+ * max_evals evaluations.  hist_x (max_evals x dim) and hist_f (max_evals)
+ * receive every evaluation in order when not NULL.  Host only. */
+int hcov_nm_minimize(hcov_objective_fn f, void* user, const double* x0, const double* steps, int dim,
+                     int max_evals, double size_tol, double* out_x, double* out_f, int* out_evals,
+                     double* hist_x, double* hist_f);
+
+/* Maximum-likelihood fit of theta = (sigma^2, ell, nu) [Sec. 5]: minimises
+ * -L~ of Eq. (2) with hcov_nm_minimize, each evaluation re-assembling C~ for
+ * its theta on the context's trees (hcov_set_theta + hcov_loglik).  Points
+ * outside the domain (or not positive definite) count as +inf.  steps: NULL
+ * for (0.01, 0.04, 0.02), the paper's initial steps reordered to
+ * (sigma^2, ell, nu).  hist_theta (max_evals x 3), hist_negll (max_evals)
+ * optional. */
+int hcov_fit(hcov_ctx* ctx, const double* z, int where, const double* theta0, const double* steps,
+             double nugget, int max_evals, double size_tol, double* out_theta, double* out_ll, int* out_evals,
+             double* hist_theta, double* hist_negll);
+
 /* Kernel timing: between hcov_profile_begin(ctx, kind) and
  * hcov_profile_end, every launch of the given stage kind (0 grouped GEMM,
  * 1 TSQR segment, 2 TSQR reduce, 3 small SVD, 4 dense leaf update/potrf,

@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
       for (int x = 0; x < 4; ++x)
 #pragma unroll
         for (int y = 0; y < 4; ++y) {
-          int gi = r0 + ty * 4 + x, gj = c0 + tx * 4 + y;
+          int gi = r0 + ty + 16 * x, gj = c0 + tx + 16 * y;
           if (gi >= pr0 && gi < pr1 && gj >= pc0 && gj < pc1)
             acc[x][y] += alpha * A[(gi - pr0) + (size_t)(gj - pc0) * lda];
         }
@@ -145,8 +145,8 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
         double av[4], bv[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          av[q] = As[kk][ty * 4 + q];
-          bv[q] = Bs[kk][tx * 4 + q];
+          av[q] = As[kk][ty + 16 * q];
+          bv[q] = Bs[kk][tx + 16 * q];
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x)
@@ -160,11 +160,11 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
   const int ldc = J.C.ld;
 #pragma unroll
   for (int x = 0; x < 4; ++x) {
-    int gi = r0 + ty * 4 + x;
+    int gi = r0 + ty + 16 * x;
     if (gi >= m) continue;
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
-      int gj = c0 + tx * 4 + y;
+      int gj = c0 + tx + 16 * y;
       if (gj >= n) continue;
       size_t o = gi + (size_t)gj * ldc;
       C[o] = J.zero ? acc[x][y] : C[o] + acc[x][y];
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__
   for (int a = 0; a < 8; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      int i = ty * 8 + a, j = tx * 8 + b;
+      int i = ty + 16 * a, j = tx + 16 * b;
       acc[a][b] = (i < p && j < q) ? Dp[i + (size_t)j * ldd] : 0.0;
     }
   // term chunks of LFK columns: 16 values per thread, loaded into registers
@@ -598,8 +598,8 @@ __global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__
       double a[8], b[8];
 #pragma unroll
       for (int x = 0; x < 8; ++x) {
-        a[x] = Us[kk * LF + ty * 8 + x];
-        b[x] = Vs[kk * LF + tx * 8 + x];
+        a[x] = Us[kk * LF + ty + 16 * x];
+        b[x] = Vs[kk * LF + tx + 16 * x];
       }
 #pragma unroll
       for (int x = 0; x < 8; ++x)
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__
     for (int a = 0; a < 8; ++a)
 #pragma unroll
       for (int b = 0; b < 8; ++b) {
-        int i = ty * 8 + a, j = tx * 8 + b;
+        int i = ty + 16 * a, j = tx + 16 * b;
         if (i < p && j < q) Dp[i + (size_t)j * ldd] = acc[a][b];
       }
     return;
@@ -626,7 +626,7 @@ __global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__
   for (int a = 0; a < 8; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-      int i = ty * 8 + a, j = tx * 8 + b;
+      int i = ty + 16 * a, j = tx + 16 * b;
       M[i + j * LF] = acc[a][b];
     }
   __shared__ int bad;
@@ -740,6 +740,9 @@ __global__ __launch_bounds__(256) void k_trsm(Bufs bufs, const int* __restrict__
       if (e < p * 64 && c < cw) Xs[i * 64 + c] = r[u];
     }
   }
+  __shared__ double rdiag[LF];
+  __syncthreads();
+  for (int i = tid; i < p; i += 256) rdiag[i] = 1.0 / Lp[i * (i + 1) / 2 + i];
   __syncthreads();
   if (J.layout != 2) {
     for (int b0 = 0; b0 < p; b0 += TB) {
@@ -747,19 +750,41 @@ __global__ __launch_bounds__(256) void k_trsm(Bufs bufs, const int* __restrict__
       if (tid < cw) {
         for (int i = b0; i < b1; ++i) {
           const double* Li = Lp + i * (i + 1) / 2;
-          double s = Xs[i * 64 + tid];
-          for (int j = b0; j < i; ++j) s -= Li[j] * Xs[j * 64 + tid];
-          Xs[i * 64 + tid] = s / Li[i];
+          double s0 = Xs[i * 64 + tid], s1 = 0.0;
+          int j = b0;
+          for (; j + 1 < i; j += 2) {
+            s0 -= Li[j] * Xs[j * 64 + tid];
+            s1 -= Li[j + 1] * Xs[(j + 1) * 64 + tid];
+          }
+          if (j < i) s0 -= Li[j] * Xs[j * 64 + tid];
+          Xs[i * 64 + tid] = (s0 + s1) * rdiag[i];
         }
       }
       __syncthreads();
-      for (int e = tid; e < (p - b1) * 64; e += 256) {
-        int c = e & 63, i = b1 + (e >> 6);
+      // rows below the block: thread owns column c = tid & 63 and rows
+      // b1 + (tid >> 6) + 4u; four independent accumulations per pass
+      {
+        const int c = tid & 63;
         if (c < cw) {
-          const double* Li = Lp + i * (i + 1) / 2;
-          double s = 0.0;
-          for (int j = b0; j < b1; ++j) s += Li[j] * Xs[j * 64 + c];
-          Xs[i * 64 + c] -= s;
+          for (int i0 = b1 + (tid >> 6); i0 < p; i0 += 16) {
+            double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+            int ro[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              int i = i0 + 4 * u;
+              ro[u] = i < p ? i * (i + 1) / 2 : 0;
+            }
+            for (int j = b0; j < b1; ++j) {
+              double xj = Xs[j * 64 + c];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) acc4[u] += Lp[ro[u] + j] * xj;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              int i = i0 + 4 * u;
+              if (i < p) Xs[i * 64 + c] -= acc4[u];
+            }
+          }
         }
       }
       __syncthreads();

@@ -22,6 +22,7 @@ class Theta(C.Structure):
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+OBJ_FN = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_int, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
@@ -75,6 +76,10 @@ def lib():
         L.hcov_tree_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int64)]
         L.hcov_tree_dump.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
         L.hcov_matern_eval.argtypes = [Theta, dp, dp, C.c_int64]
+        L.hcov_nm_minimize.argtypes = [OBJ_FN, C.c_void_p, dp, dp, C.c_int, C.c_int, C.c_double, dp, dp,
+                                       C.POINTER(C.c_int), dp, dp]
+        L.hcov_fit.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, C.c_double, C.c_int, C.c_double, dp, dp,
+                               C.POINTER(C.c_int), dp, dp]
         L.hcov_profile_begin.argtypes = [C.c_void_p, C.c_int]
         L.hcov_profile_end.argtypes = [C.c_void_p, C.POINTER(C.c_int64), dp, dp]
         _lib = L
@@ -84,7 +89,7 @@ def lib():
 EXPORTS = ["hcov_opts_default", "hcov_build", "hcov_set_theta", "hcov_cholesky", "hcov_logdet", "hcov_solve",
            "hcov_forward", "hcov_sample", "hcov_matvec", "hcov_loglik", "hcov_stats", "hcov_estimate_bytes",
            "hcov_perm", "hcov_destroy", "hcov_strerror", "hcov_last_error", "hcov_tree_sizes", "hcov_tree_dump",
-           "hcov_matern_eval", "hcov_profile_begin", "hcov_profile_end"]
+           "hcov_matern_eval", "hcov_profile_begin", "hcov_profile_end", "hcov_nm_minimize", "hcov_fit"]
 
 STAGE_KINDS = {"gemm": 0, "tsqr_seg": 1, "tsqr_red": 2, "small": 3, "leaf": 4, "trsm": 5}
 
@@ -138,6 +143,27 @@ def matern_eval(theta, h):
     if rc:
         raise HcovError(rc, lib().hcov_strerror(rc).decode())
     return out
+
+
+def nm_minimize(f, x0, steps, max_evals=200, size_tol=1e-5):
+    """Library Nelder-Mead on a Python objective f(x) -> float.  Returns
+    (x, f(x), n_evals, history list of (x, f))."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    st = np.ascontiguousarray(steps, dtype=np.float64)
+    d = x0.size
+    cb = OBJ_FN(lambda xp, dim, user: float(f(np.array([xp[i] for i in range(dim)]))))
+    ox = np.empty(d)
+    of = C.c_double()
+    ne = C.c_int()
+    hx = np.empty(max_evals * d)
+    hf = np.empty(max_evals)
+    rc = lib().hcov_nm_minimize(cb, None, _dp(x0), _dp(st), d, int(max_evals), float(size_tol), _dp(ox),
+                                C.byref(of), C.byref(ne), _dp(hx), _dp(hf))
+    if rc:
+        raise HcovError(rc, lib().hcov_strerror(rc).decode())
+    n = ne.value
+    hist = [(hx[i * d:(i + 1) * d].copy(), hf[i]) for i in range(n)]
+    return ox, of.value, n, hist
 
 
 def estimate_bytes(locs, eps, leaf, eta, opts=None):
@@ -258,6 +284,24 @@ class HCov:
         s = Stats()
         self._chk(lib().hcov_stats(self._ctx, C.byref(s)))
         return {f: getattr(s, f) for f, _ in Stats._fields_}
+
+    def fit(self, z, theta0, nugget, max_evals=30, size_tol=1e-5, steps=None):
+        """Maximum-likelihood theta = (sigma2, ell, nu) by the library's
+        Nelder-Mead on the H-likelihood.  Returns (theta, loglik, n_evals,
+        history of (theta, -loglik))."""
+        p, w, keep = self._vec(z)
+        t0 = np.ascontiguousarray(theta0, dtype=np.float64)
+        st = None if steps is None else np.ascontiguousarray(steps, dtype=np.float64)
+        out = np.empty(3)
+        ll = C.c_double()
+        ne = C.c_int()
+        ht = np.empty(max_evals * 3)
+        hf = np.empty(max_evals)
+        self._chk(lib().hcov_fit(self._ctx, p, w, _dp(t0), _dp(st) if st is not None else None, float(nugget),
+                                 int(max_evals), float(size_tol), _dp(out), C.byref(ll), C.byref(ne), _dp(ht),
+                                 _dp(hf)))
+        n = ne.value
+        return out, ll.value, n, [(ht[3 * i:3 * i + 3].copy(), hf[i]) for i in range(n)]
 
     def profile_begin(self, kind):
         self._chk(lib().hcov_profile_begin(self._ctx, STAGE_KINDS[kind] if isinstance(kind, str) else int(kind)))
