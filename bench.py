@@ -24,6 +24,10 @@ sys.path.insert(0, ROOT)
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (= FP64 matrix) peak
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def cpu_baseline(n_full, theta, budget_s=20.0):
     """Dense FP64 oracle (NumPy + LAPACK) on a bounded sample of the same
     workload, scaled to evaluations per second at n_full by the n^3 cost of
@@ -84,6 +88,7 @@ def main():
     t_build = time.perf_counter()
     H = hcov.HCov(locs, theta0, eps=eps, leaf=leaf, eta=eta, stream=stream)
     t_build = time.perf_counter() - t_build
+    progress(f"trees, plan and first assembly at n={n}: {t_build:.1f} s")
     # synthetic observations: a sample Z = L~ xi of the field at theta0
     H.cholesky()
     perm = H.perm()
@@ -91,6 +96,7 @@ def main():
     thetas = workloads.theta_perturbations(theta0[:3], args.warmup + args.steps, rel=0.10, seed=0)
     thetas = [(float(a), float(b), float(c), theta0[3]) for a, b, c in thetas]
     z_dev = torch.from_numpy(z).to("cuda")
+    progress("synthetic observations drawn")
 
     def step(th):
         H.set_theta(th)
@@ -98,6 +104,7 @@ def main():
 
     for i in range(args.warmup):
         step(thetas[i])
+        progress(f"warmup step {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     lat = []
     lls = []
@@ -108,6 +115,7 @@ def main():
         s0 = time.perf_counter()
         lls.append(step(thetas[args.warmup + i])[0])
         lat.append(time.perf_counter() - s0)
+        progress(f"timed step {i + 1}/{args.steps}: {lat[-1]:.3f} s")
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     launches, kern_ms, kern_flops = H.profile_end()
@@ -149,6 +157,7 @@ def main():
         "loglik_last": lls[-1],
     }
     if not args.no_cpu:
+        progress("timing the CPU oracle on a bounded sample")
         rec["cpu_baseline"] = cpu_baseline(n, theta0)
     print(json.dumps(rec))
 

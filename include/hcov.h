@@ -47,6 +47,7 @@ extern "C" {
 #define HCOV_ESTATE -4      /* call out of order (e.g. logdet before cholesky) */
 #define HCOV_EDEVICE -5     /* HIP runtime error or no device */
 #define HCOV_ERANK -6       /* a low-rank block needed more than max_rank */
+#define HCOV_EAGAIN -7      /* serving: the request has not completed yet */
 
 #define HCOV_HOST 0
 #define HCOV_DEVICE 1
@@ -246,6 +247,67 @@ int hcov_tree_sizes(const hcov_ctx* ctx, int* depth, int64_t* n_blocks);
  * (level, row node, column node, kind) with kind 1 = low rank, 0 = dense, in
  * breadth-first order. */
 int hcov_tree_dump(const hcov_ctx* ctx, double* bbox, int64_t* blocks);
+
+/* ------------------------------------------------------------ serving
+ * A request loop for many likelihood evaluations of different n and theta
+ * (an optimiser re-evaluating one data set, or independent data sets).  The
+ * server owns `slots` worker threads, each with its own HIP stream, so that
+ * up to `slots` evaluations run concurrently and their kernels overlap on
+ * the GPU.  Requests are admitted in arrival order as soon as a slot is free
+ * and the estimate of their device memory (hcov_estimate_bytes) fits in the
+ * remaining budget; a request larger than the whole budget runs alone.
+ * Every evaluation is the same computation as hcov_build + hcov_loglik on
+ * its own context, so its result does not depend on the other requests.
+ *
+ * Data sets registered with hcov_server_dataset stay resident (trees, plan
+ * and factor storage), and requests naming them only re-assemble and
+ * re-factorise for the new theta [HLIBCov Sec. 4: the likelihood is
+ * maximised over theta for fixed locations]; their memory is charged to the
+ * budget until hcov_server_release.  Requests on one data set run one at a
+ * time in arrival order.
+ *
+ * All server calls are thread safe.  The server must be destroyed before the
+ * process exits; hcov_server_destroy waits for the admitted requests and
+ * drops the queued ones. */
+typedef struct hcov_server hcov_server;
+
+typedef struct {
+  const double* locs;   /* host n x 2 locations (copied at submit); NULL
+                           when `dataset` names a resident data set */
+  int64_t n;            /* number of locations (= the data set's n) */
+  const double* z;      /* host observations, external order (copied) */
+  hcov_theta theta;
+  double eps;           /* used only without a data set */
+  int leaf;
+  double eta;
+  int dataset;          /* 0, or an id from hcov_server_dataset */
+} hcov_request;
+
+typedef struct {
+  int status;           /* HCOV_OK or the evaluation's error code */
+  double loglik, logdet, quad;   /* as hcov_loglik */
+  double queue_ms;      /* submit -> admission */
+  double service_ms;    /* admission -> completion */
+  double latency_ms;    /* submit -> completion */
+} hcov_result;
+
+/* slots in [1, 64]; mem_budget_bytes = 0: 90% of the device memory free at
+ * creation; opts: build options of every context (NULL = defaults; the
+ * allocator fields are replaced by stream-ordered allocation). */
+int hcov_server_create(int slots, size_t mem_budget_bytes, const hcov_opts* opts, hcov_server** out);
+/* Registers a resident data set (built now, on its own stream). */
+int hcov_server_dataset(hcov_server* s, const double* locs, int64_t n, hcov_theta theta, double eps, int leaf,
+                        double eta, int* id);
+/* Frees a data set once its queued requests have run. */
+int hcov_server_release(hcov_server* s, int id);
+/* Queues a request; *ticket identifies its result. */
+int hcov_server_submit(hcov_server* s, const hcov_request* req, uint64_t* ticket);
+/* HCOV_OK and *out filled when done (the result is then forgotten),
+ * HCOV_EAGAIN while queued or running, HCOV_EINVAL for unknown tickets. */
+int hcov_server_poll(hcov_server* s, uint64_t ticket, hcov_result* out);
+/* Blocks until the request is done, then as hcov_server_poll. */
+int hcov_server_wait(hcov_server* s, uint64_t ticket, hcov_result* out);
+void hcov_server_destroy(hcov_server* s);
 
 #ifdef __cplusplus
 }

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhcov.so")
-SOURCES = ["plan.cpp", "nm.cpp", "tree.hip", "kernels.hip", "aca_big.hip", "hcov.hip"]
+SOURCES = ["plan.cpp", "nm.cpp", "tree.hip", "kernels.hip", "aca_big.hip", "hcov.hip", "server.hip"]
 FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

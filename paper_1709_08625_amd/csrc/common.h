@@ -22,7 +22,12 @@ enum StatusBits : int {
   STAT_NONFINITE = 8,       // non-finite matrix entry
 };
 
-__device__ __forceinline__ double* refp(const Bufs& b, const Ref& r) { return b.p[r.buf] + r.off; }
+// The buffer table lives in device memory (one per context): a uniform
+// index into it is a scalar load, whereas a dynamically indexed
+// kernel-argument array would be copied to scratch memory.
+__device__ __forceinline__ double* refp(const Bufs* __restrict__ b, const Ref& r) {
+  return b->p[r.buf] + r.off;
+}
 
 __device__ __forceinline__ int dimv(const int* __restrict__ dyn, const Dim& d) {
   if (d.slot < 0) return d.maxv;

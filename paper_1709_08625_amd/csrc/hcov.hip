@@ -2,6 +2,8 @@
 // Declarations and citations are in include/hcov.h.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -66,7 +68,7 @@ struct hcov_ctx {
 namespace {
 
 const char* kErr[] = {"ok", "invalid argument", "matrix not positive definite", "out of memory",
-                      "call out of order", "device error", "rank capacity exceeded"};
+                      "call out of order", "device error", "rank capacity exceeded", "not completed yet"};
 
 int fail(hcov_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
@@ -212,14 +214,7 @@ double stage_flops(const Plan& P, const std::vector<int>& dyn, const Stage& s) {
       }
     }
   } else if (s.kind == ST_LEAF) {
-    for (int t = s.begin; t < s.end; ++t) {
-      const LeafJob& J = P.leafs[t];
-      for (int q = J.t0; q < J.t1; ++q) {
-        const LeafTerm& T = P.lterms[q];
-        f += 2.0 * dyn_value(dyn, T.k) * double(T.mi) * double(T.nj);
-      }
-      if (J.diag) f += double(J.p) * J.p * J.p / 3.0;
-    }
+    for (int t = s.begin; t < s.end; ++t) f += double(P.leafs[t].p) * P.leafs[t].p * P.leafs[t].p / 3.0;
   } else if (s.kind == ST_TRSM) {
     for (int t = s.begin; t < s.end; ++t) {
       const TrsmJob& J = P.trsms[t];
@@ -355,7 +350,7 @@ void hcov_opts_default(hcov_opts* o) {
 }
 
 const char* hcov_strerror(int code) {
-  if (code > 0 || code < -6) return "unknown error";
+  if (code > 0 || code < -7) return "unknown error";
   return kErr[-code];
 }
 
@@ -389,13 +384,12 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   c->stream = (hipStream_t)hip_stream;
   c->theta = theta;
   c->D = tree_depth(n, leaf);
-  static bool attr_done = false;
-  if (!attr_done) {
-    if (setup_kernel_attributes() != hipSuccess) {
-      delete c;
-      return HCOV_EDEVICE;
-    }
-    attr_done = true;
+  static std::once_flag attr_once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(attr_once, [] { attr_err = setup_kernel_attributes(); });
+  if (attr_err != hipSuccess) {
+    delete c;
+    return HCOV_EDEVICE;
   }
   auto bail = [&](int code) {
     hcov_destroy(c);
@@ -415,16 +409,18 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
     }
     lo[l][2 * cnt] = n;
   }
+  // temporaries of the tree build are stream ordered (no device-wide sync)
   double* d_orig = nullptr;
-  if (hipMalloc(&d_orig, n * 16) != hipSuccess) return bail(HCOV_ENOMEM);
-  if (hipMemcpy(d_orig, h.data(), n * 16, hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(d_orig);
+  if (hipMallocAsync(&d_orig, n * 16, c->stream) != hipSuccess) return bail(HCOV_ENOMEM);
+  if (hipMemcpyAsync(d_orig, h.data(), n * 16, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipFreeAsync(d_orig, c->stream);
     return bail(HCOV_EDEVICE);
   }
   TreeOut T;
   std::string e = build_trees(d_orig, n, leaf, c->D, eta, lo, c->stream, T);
   if (!e.empty()) {
-    hipFree(d_orig);
+    (void)hipFreeAsync(d_orig, c->stream);
     c->err = e;
     return bail(HCOV_EDEVICE);
   }
@@ -436,8 +432,8 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   c->d_perm = (int*)dev_alloc(c, n * 4);
   c->d_loc = (double*)dev_alloc(c, n * 16);
   if (!c->d_perm || !c->d_loc) {
-    hipFree(d_orig);
-    hipFree(T.d_perm);
+    (void)hipFreeAsync(d_orig, c->stream);
+    (void)hipFreeAsync(T.d_perm, c->stream);
     return bail(HCOV_ENOMEM);
   }
   hipMemcpyAsync(c->d_perm, T.d_perm, n * 4, hipMemcpyDeviceToDevice, c->stream);
@@ -448,10 +444,10 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
       lc[2 * i + 1] = h[2 * T.perm[i] + 1];
     }
     hipMemcpyAsync(c->d_loc, lc.data(), n * 16, hipMemcpyHostToDevice, c->stream);
+    (void)hipFreeAsync(d_orig, c->stream);
+    (void)hipFreeAsync(T.d_perm, c->stream);
     hipStreamSynchronize(c->stream);
   }
-  hipFree(d_orig);
-  hipFree(T.d_perm);
   // plan
   int64_t nb = int64_t(c->blocks_lac.size() / 4);
   e = build_plan(c->plan, n, c->D, leaf, c->blocks_lac.data(), nb, o.max_rank, 10, o.precision == HCOV_MIXED);
@@ -544,6 +540,8 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   c->d_aca = upload(c, aj);
   LaunchCtx& L = c->L;
   for (int b = 0; b < B_COUNT; ++b) L.bufs.p[b] = c->d_buf[b];
+  std::vector<Bufs> btab(1, L.bufs);
+  L.dbufs = upload(c, btab);
   L.dyn = c->d_dyn;
   L.gjobs = upload(c, P.gjobs);
   L.gprods = upload(c, P.gprods);
@@ -552,7 +550,6 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   L.treds = upload(c, P.treds);
   L.smalls = upload(c, P.smalls);
   L.leafs = upload(c, P.leafs);
-  L.lterms = upload(c, P.lterms);
   L.trsms = upload(c, P.trsms);
   L.copy_pairs = upload(c, cp);
   L.n_copy = int(cp.size());
@@ -561,7 +558,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   L.tau = std::min(1e-10, 1e-2 * eps);
   L.logdet = c->d_logdet;
   L.status = c->d_status;
-  if (!L.gjobs || !L.gprods || !L.gtiles || !L.tsegs || !L.treds || !L.smalls || !L.leafs || !L.lterms ||
+  if (!L.dbufs || !L.gjobs || !L.gprods || !L.gtiles || !L.tsegs || !L.treds || !L.smalls || !L.leafs ||
       !L.trsms || !L.copy_pairs || !c->d_fill || !c->d_aca)
     return bail(HCOV_ENOMEM);
   if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(HCOV_EDEVICE);
@@ -723,7 +720,9 @@ int hcov_stats(const hcov_ctx* c, hcov_stats_t* s) {
   s->n_launches_factor = P.n_launch_fact;
   // ranks
   std::vector<int> dyn(P.n_dyn + 1);
-  if (hipMemcpy(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) return HCOV_EDEVICE;
+  if (hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return HCOV_EDEVICE;
   int64_t sum = 0, rows = 0, mx = 0;
   double fb = double(P.dense_elems);
   for (auto& B : P.blocks) {
@@ -806,7 +805,8 @@ int hcov_profile_end(hcov_ctx* c, int64_t* launches, double* total_ms, double* f
   if (!c) return HCOV_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::vector<int> dyn(c->plan.n_dyn + 1);
-  HIPCHK(c, hipMemcpy(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   double ms = 0.0, fl = 0.0;
   for (size_t i = 0; i < c->prof_ev.size(); ++i) {
     float t = 0.f;

@@ -5,7 +5,7 @@
 //   k_tsqr_red   R factor of a stack of segment R factors
 //   k_small      one-sided Jacobi SVDs of the small R-factor products
 //                (recompression and randomised-sketch truncation)
-//   k_leaf       dense leaf targets: Schur update in registers, potrf in LDS
+//   k_leaf       dense leaf targets: partial-sum update, blocked potrf
 //   k_trsm       triangular solves with a diagonal leaf factor
 //   k_dense_fill Matérn entries of the dense leaves (+ nugget, Sec. 5.2)
 //   k_aca        partially pivoted ACA of admissible blocks
@@ -24,28 +24,26 @@ namespace hc {
 // ------------------------------------------------------------------ GEMM
 // One work-group (256 threads) computes a 64 x 64 tile of one job's output:
 // C_tile = (zero ? 0 : C_tile) + sum_p alpha_p op(A_p) op(B_p) restricted to
-// the tile, accumulating all products of the job in registers (each thread
-// owns a 4 x 4 sub-tile).  k is streamed through LDS in chunks of 16.
-constexpr int GT = 64, GK = 16;
+// the tile, accumulating all products of the job in registers.  Thread
+// (ty, tx) owns rows ty + 16x and columns tx + 16y of the tile; when the
+// live part of the tile (ranks are known only at run time) is at most 16 or
+// 32 rows/columns wide, only NX x NY of the 4 x 4 sub-tile are computed.
+// k is streamed through LDS in chunks of GK with the next chunk's global
+// loads in flight in registers while the current one is consumed.
+constexpr int GT = 64, GK = 32;
+constexpr int GR = GK * GT / 256;   // elements of each operand chunk per thread
 
-__global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__ dyn,
-                                              const GemmJob* __restrict__ jobs,
-                                              const GemmProd* __restrict__ prods,
-                                              const GemmTile* __restrict__ tiles, int t0) {
-  const GemmTile T = tiles[t0 + blockIdx.x];
-  const GemmJob J = jobs[T.job];
-  const int m = dimv(dyn, J.m), n = dimv(dyn, J.n);
-  const int r0 = T.ti * GT, c0 = T.tj * GT;
-  if (r0 >= m || c0 >= n) return;
-  __shared__ double As[GK][GT + 1];
-  __shared__ double Bs[GK][GT + 1];
+template <int NX, int NY>
+__device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const int* __restrict__ dyn, const GemmJob& J,
+                                          const GemmProd* __restrict__ prods, int m, int n, int r0,
+                                          int c0, double (*As)[GT + 1], double (*Bs)[GT + 1]) {
   const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  double acc[4][4];
+  const int ty = tid & 15, tx = tid >> 4;   // rows follow the lane index (coalesced C and tb==2 access)
+  double acc[NX][NY];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < NX; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < NY; ++b) acc[a][b] = 0.0;
 
   for (int pi = J.p0; pi < J.p1; ++pi) {
     const GemmProd Pd = prods[pi];
@@ -60,32 +58,26 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
     const int lda = Pd.A.ld, ldb = Pd.B.ld;
     const double alpha = Pd.alpha;
     if (Pd.tb == 2) {
-      // C += alpha * A (element-wise; partial sums of a split product)
+      // C += alpha * A (element-wise; partial sums of a split job)
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int x = 0; x < NX; ++x)
 #pragma unroll
-        for (int y = 0; y < 4; ++y) {
+        for (int y = 0; y < NY; ++y) {
           int gi = r0 + ty + 16 * x, gj = c0 + tx + 16 * y;
           if (gi >= pr0 && gi < pr1 && gj >= pc0 && gj < pc1)
             acc[x][y] += alpha * A[(gi - pr0) + (size_t)(gj - pc0) * lda];
         }
       continue;
     }
-    // register prefetch of the next 16-wide k chunk while the current one is
-    // consumed from LDS
-    double ra[4], rb[4];
+    // element e of a chunk: A chunk is GT x GK, B chunk GK x GT; the index
+    // split follows the operand's storage order so that lanes coalesce
+    double ra[GR], rb[GR];
     auto fetch = [&](int k0) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < GR; ++r) {
         int e = tid + 256 * r;
-        int ii, kk;
-        if (Pd.ta == 0) {
-          ii = e & 63;
-          kk = e >> 6;
-        } else {
-          ii = e >> 4;
-          kk = e & 15;
-        }
+        int ii = Pd.ta == 0 ? (e & (GT - 1)) : (e / GK);
+        int kk = Pd.ta == 0 ? (e / GT) : (e & (GK - 1));
         int gi = r0 + ii, gk = k0 + kk;
         double v = 0.0;
         if (gi >= pr0 && gi < pr1 && gk < k) {
@@ -95,16 +87,10 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
         ra[r] = alpha * v;
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < GR; ++r) {
         int e = tid + 256 * r;
-        int jj, kk;
-        if (Pd.tb == 0) {
-          kk = e & 15;
-          jj = e >> 4;
-        } else {
-          jj = e & 63;
-          kk = e >> 6;
-        }
+        int kk = Pd.tb == 0 ? (e & (GK - 1)) : (e / GT);
+        int jj = Pd.tb == 0 ? (e / GK) : (e & (GT - 1));
         int gj = c0 + jj, gk = k0 + kk;
         double v = 0.0;
         if (gj >= pc0 && gj < pc1 && gk < k) {
@@ -117,41 +103,29 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
     fetch(0);
     for (int k0 = 0; k0 < k; k0 += GK) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
+      for (int r = 0; r < GR; ++r) {
         int e = tid + 256 * r;
-        int ii, kk;
-        if (Pd.ta == 0) {
-          ii = e & 63;
-          kk = e >> 6;
-        } else {
-          ii = e >> 4;
-          kk = e & 15;
-        }
+        int ii = Pd.ta == 0 ? (e & (GT - 1)) : (e / GK);
+        int kk = Pd.ta == 0 ? (e / GT) : (e & (GK - 1));
         As[kk][ii] = ra[r];
-        int jj, k2;
-        if (Pd.tb == 0) {
-          k2 = e & 15;
-          jj = e >> 4;
-        } else {
-          jj = e & 63;
-          k2 = e >> 6;
-        }
+        int k2 = Pd.tb == 0 ? (e & (GK - 1)) : (e / GT);
+        int jj = Pd.tb == 0 ? (e / GK) : (e & (GT - 1));
         Bs[k2][jj] = rb[r];
       }
       __syncthreads();
       if (k0 + GK < k) fetch(k0 + GK);
+      const int kl = min(GK, k - k0);
+#pragma unroll 8
+      for (int kk = 0; kk < kl; ++kk) {
+        double av[NX], bv[NY];
 #pragma unroll
-      for (int kk = 0; kk < GK; ++kk) {
-        double av[4], bv[4];
+        for (int q = 0; q < NX; ++q) av[q] = As[kk][ty + 16 * q];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          av[q] = As[kk][ty + 16 * q];
-          bv[q] = Bs[kk][tx + 16 * q];
-        }
+        for (int q = 0; q < NY; ++q) bv[q] = Bs[kk][tx + 16 * q];
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+        for (int x = 0; x < NX; ++x)
 #pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
+          for (int y = 0; y < NY; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
       }
       __syncthreads();
     }
@@ -159,16 +133,42 @@ __global__ __launch_bounds__(256) void k_gemm(Bufs bufs, const int* __restrict__
   double* __restrict__ C = refp(bufs, J.C);
   const int ldc = J.C.ld;
 #pragma unroll
-  for (int x = 0; x < 4; ++x) {
+  for (int x = 0; x < NX; ++x) {
     int gi = r0 + ty + 16 * x;
     if (gi >= m) continue;
 #pragma unroll
-    for (int y = 0; y < 4; ++y) {
+    for (int y = 0; y < NY; ++y) {
       int gj = c0 + tx + 16 * y;
       if (gj >= n) continue;
       size_t o = gi + (size_t)gj * ldc;
       C[o] = J.zero ? acc[x][y] : C[o] + acc[x][y];
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemm(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
+                                              const GemmJob* __restrict__ jobs,
+                                              const GemmProd* __restrict__ prods,
+                                              const GemmTile* __restrict__ tiles, int t0) {
+  const GemmTile T = tiles[t0 + blockIdx.x];
+  const GemmJob J = jobs[T.job];
+  const int m = dimv(dyn, J.m), n = dimv(dyn, J.n);
+  const int r0 = T.ti * GT, c0 = T.tj * GT;
+  if (r0 >= m || c0 >= n) return;
+  __shared__ double As[GK][GT + 1];
+  __shared__ double Bs[GK][GT + 1];
+  const int er = min(GT, m - r0), ec = min(GT, n - c0);
+  const int nx = er <= 16 ? 1 : (er <= 32 ? 2 : 4), ny = ec <= 16 ? 1 : (ec <= 32 ? 2 : 4);
+  switch (nx * 8 + ny) {
+    case 9: gemm_tile<1, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 10: gemm_tile<1, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 12: gemm_tile<1, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 17: gemm_tile<2, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 18: gemm_tile<2, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 20: gemm_tile<2, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 33: gemm_tile<4, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 34: gemm_tile<4, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    default: gemm_tile<4, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
   }
 }
 
@@ -219,7 +219,7 @@ __device__ void house_qr_lds(double* M, int ldm, int mrows, int c, double* red) 
 
 __device__ __forceinline__ int qr_ldm(int c) { return QR_LDS / (c > 0 ? c : 1); }
 
-__global__ __launch_bounds__(256) void k_tsqr_seg(Bufs bufs, const int* __restrict__ dyn,
+__global__ __launch_bounds__(256) void k_tsqr_seg(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
                                                   const TsqrSeg* __restrict__ segs, int s0, int rmax) {
   const TsqrSeg S = segs[s0 + blockIdx.x];
   const int c = dimv(dyn, S.cols);
@@ -230,12 +230,11 @@ __global__ __launch_bounds__(256) void k_tsqr_seg(Bufs bufs, const int* __restri
   const int tid = threadIdx.x;
   if (c <= 0) return;
   const int ldm = qr_ldm(c);
-  const int chunk = ldm - c;
   const double* __restrict__ X = refp(bufs, S.X);
   const int ld = S.X.ld;
   int have = 0;
-  for (int base = 0; base < S.rows; base += chunk) {
-    int nr = min(chunk, S.rows - base);
+  for (int base = 0, nr = 0; base < S.rows; base += nr) {
+    nr = min(ldm - have, S.rows - base);
     for (int b0 = 0; b0 < nr * c; b0 += 2048) {
       double r[8];
 #pragma unroll
@@ -262,7 +261,7 @@ __global__ __launch_bounds__(256) void k_tsqr_seg(Bufs bufs, const int* __restri
   }
 }
 
-__global__ __launch_bounds__(256) void k_tsqr_red(Bufs bufs, const int* __restrict__ dyn,
+__global__ __launch_bounds__(256) void k_tsqr_red(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
                                                   const TsqrRed* __restrict__ reds, int r0i, int rmax) {
   const TsqrRed S = reds[r0i + blockIdx.x];
   const int c = dimv(dyn, S.cols);
@@ -305,10 +304,13 @@ __global__ __launch_bounds__(256) void k_tsqr_red(Bufs bufs, const int* __restri
 // One-sided Jacobi (Hestenes) on the columns of an n x n matrix A in LDS
 // (ld = SM), accumulating the right rotations in V: A V = U S.  All disjoint
 // column pairs of a round-robin round are processed at once, each by a group
-// of g lanes (g a power of two, groups aligned inside a wave).
+// of g lanes (g a power of two, groups aligned inside a wave).  Pairs of
+// columns whose squared norms are both below thr2 are skipped: callers set
+// thr2 well below their truncation threshold, and such pairs only slow the
+// convergence.
 constexpr int SM = 80;
 
-__device__ void jacobi_svd_lds(double* A, double* V, int n, double* red) {
+__device__ void jacobi_svd_lds(double* A, double* V, int n, double thr2, double* red) {
   const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += 256) {
     int i = e % n, j = e / n;
@@ -320,9 +322,11 @@ __device__ void jacobi_svd_lds(double* A, double* V, int n, double* red) {
   while (g > 1 && npairs * g > 256) g >>= 1;
   const int grp = tid / g, gl = tid % g;
   const double tol = fmax(1e-14, 8.0 * 2.220446049250313e-16 * n);
+  const double tol2 = tol * tol;
+  constexpr int RU = 8;   // rows per lane kept in registers during a rotation
   __syncthreads();
   for (int sweep = 0; sweep < 30; ++sweep) {
-    double offmax = 0.0;
+    double off2 = 0.0;   // max over pairs of ga^2 / (al be)
     for (int rnd = 0; rnd < np - 1; ++rnd) {
       if (grp < npairs) {
         int a, b;
@@ -335,33 +339,64 @@ __device__ void jacobi_svd_lds(double* A, double* V, int n, double* red) {
         }
         if (a < n && b < n) {
           const int pp = min(a, b), qq = max(a, b);
+          double* __restrict__ Ap = A + pp * SM;
+          double* __restrict__ Aq = A + qq * SM;
+          double xr[RU], yr[RU];
           double al = 0.0, be = 0.0, ga = 0.0;
-          for (int i = gl; i < n; i += g) {
-            double x = A[i + pp * SM], y = A[i + qq * SM];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            const int i = gl + g * u;
+            xr[u] = i < n ? Ap[i] : 0.0;
+            yr[u] = i < n ? Aq[i] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            al = fma(xr[u], xr[u], al);
+            be = fma(yr[u], yr[u], be);
+            ga = fma(xr[u], yr[u], ga);
+          }
+          for (int i = gl + g * RU; i < n; i += g) {
+            double x = Ap[i], y = Aq[i];
+            al = fma(x, x, al);
+            be = fma(y, y, be);
+            ga = fma(x, y, ga);
           }
           for (int o = g >> 1; o > 0; o >>= 1) {
             al += __shfl_xor(al, o);
             be += __shfl_xor(be, o);
             ga += __shfl_xor(ga, o);
           }
-          if (ga != 0.0 && al != 0.0 && be != 0.0) {
-            double rel = fabs(ga) / sqrt(al * be);
-            offmax = fmax(offmax, rel);
-            if (rel >= tol) {
-              double zeta = (be - al) / (2.0 * ga);
-              double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-              double cs = 1.0 / sqrt(1.0 + tt * tt);
-              double sn = cs * tt;
+          if (ga != 0.0 && al != 0.0 && be != 0.0 && (al >= thr2 || be >= thr2)) {
+            const double g2 = ga * ga, ab = al * be;
+            off2 = fmax(off2, g2 / ab);
+            if (g2 >= tol2 * ab) {
+              // tangent of the rotation angle: the smaller root of
+              // t^2 + 2 zeta t - 1 = 0, zeta = (be - al) / (2 ga), written
+              // without the division by ga
+              const double d = be - al;
+              const double h = sqrt(fma(d, d, 4.0 * g2));
+              const double tt = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + h);
+              const double cs = 1.0 / sqrt(fma(tt, tt, 1.0));
+              const double sn = cs * tt;
+#pragma unroll
+              for (int u = 0; u < RU; ++u) {
+                const int i = gl + g * u;
+                if (i < n) {
+                  Ap[i] = cs * xr[u] - sn * yr[u];
+                  Aq[i] = sn * xr[u] + cs * yr[u];
+                }
+              }
+              for (int i = gl + g * RU; i < n; i += g) {
+                double x = Ap[i], y = Aq[i];
+                Ap[i] = cs * x - sn * y;
+                Aq[i] = sn * x + cs * y;
+              }
+              double* __restrict__ Vp = V + pp * SM;
+              double* __restrict__ Vq = V + qq * SM;
               for (int i = gl; i < n; i += g) {
-                double x = A[i + pp * SM], y = A[i + qq * SM];
-                A[i + pp * SM] = cs * x - sn * y;
-                A[i + qq * SM] = sn * x + cs * y;
-                double vx = V[i + pp * SM], vy = V[i + qq * SM];
-                V[i + pp * SM] = cs * vx - sn * vy;
-                V[i + qq * SM] = sn * vx + cs * vy;
+                double vx = Vp[i], vy = Vq[i];
+                Vp[i] = cs * vx - sn * vy;
+                Vq[i] = sn * vx + cs * vy;
               }
             }
           }
@@ -369,14 +404,29 @@ __device__ void jacobi_svd_lds(double* A, double* V, int n, double* red) {
       }
       __syncthreads();
     }
-    // block max of offmax
-    for (int o = 32; o > 0; o >>= 1) offmax = fmax(offmax, __shfl_xor(offmax, o));
-    if ((tid & 63) == 0) red[tid >> 6] = offmax;
+    for (int o = 32; o > 0; o >>= 1) off2 = fmax(off2, __shfl_xor(off2, o));
+    if ((tid & 63) == 0) red[tid >> 6] = off2;
     __syncthreads();
     double om = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     __syncthreads();
-    if (om < tol) break;
+    if (om < tol2) break;
   }
+}
+
+// Squared Frobenius norm of the n x n matrix A in LDS, returned to every
+// thread (uses red[4..7]).
+__device__ double fro2_lds(const double* A, int n, double* red) {
+  const int tid = threadIdx.x;
+  double f = 0.0;
+  for (int e = tid; e < n * n; e += 256) {
+    double v = A[(e % n) + (e / n) * SM];
+    f += v * v;
+  }
+  for (int o = 32; o > 0; o >>= 1) f += __shfl_xor(f, o);
+  __syncthreads();
+  if ((tid & 63) == 0) red[4 + (tid >> 6)] = f;
+  __syncthreads();
+  return red[4] + red[5] + red[6] + red[7];
 }
 
 // singular values (column norms of A) and the order by decreasing value,
@@ -420,7 +470,126 @@ __device__ void load_upper(const double* __restrict__ R, int ld, int n, double* 
   }
 }
 
-__global__ __launch_bounds__(256) void k_small(Bufs bufs, int* __restrict__ dyn,
+// Rank-revealing orthogonalisation of a sketch: Householder QR with column
+// pivoting of the n x n upper-triangular R_Y in LDS (A, ld SM), stopped at
+// the first pivot |R'_jj| <= tau |R'_00|.  Returns the kept count k; on exit
+// A holds R' in its leading k x k upper triangle and piv[0..k) the chosen
+// columns.  Column norms are downdated and recomputed when the downdate
+// loses more than half of the digits.
+__device__ int qrcp_lds(double* A, int n, double tau, double* cn, double* cn0, int* piv,
+                        double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ int s_piv, s_stop;
+  for (int j = tid; j < n; j += 256) {
+    double c = 0.0;
+    for (int i = 0; i <= j; ++i) c += A[i + j * SM] * A[i + j * SM];
+    cn[j] = c;
+    cn0[j] = c;
+    piv[j] = j;
+  }
+  if (tid == 0) s_stop = n;
+  __syncthreads();
+  int k = n;
+  for (int j = 0; j < n; ++j) {
+    // pivot: the largest remaining norm, ties to the lowest column
+    if (wave == 0) {
+      double bv = -1.0;
+      int bi = n;
+      for (int l = j + lane; l < n; l += 64)
+        if (cn[l] > bv) {
+          bv = cn[l];
+          bi = l;
+        }
+      for (int o = 32; o > 0; o >>= 1) {
+        double ov = __shfl_xor(bv, o);
+        int oi = __shfl_xor(bi, o);
+        if (ov > bv || (ov == bv && oi < bi)) {
+          bv = ov;
+          bi = oi;
+        }
+      }
+      if (lane == 0) s_piv = bi;
+    }
+    __syncthreads();
+    const int p = s_piv;
+    if (p != j) {
+      for (int i = tid; i < n; i += 256) {
+        double t = A[i + j * SM];
+        A[i + j * SM] = A[i + p * SM];
+        A[i + p * SM] = t;
+      }
+      if (tid == 0) {
+        double t = cn[j];
+        cn[j] = cn[p];
+        cn[p] = t;
+        t = cn0[j];
+        cn0[j] = cn0[p];
+        cn0[p] = t;
+        int q = piv[j];
+        piv[j] = piv[p];
+        piv[p] = q;
+      }
+    }
+    __syncthreads();
+    // Householder reflector of column j, rows j..n-1 (exact norm)
+    if (wave == 0) {
+      double sq = 0.0;
+      for (int i = j + lane; i < n; i += 64) sq += A[i + j * SM] * A[i + j * SM];
+      for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+      if (lane == 0) {
+        const double nrm = sqrt(sq);
+        if (j == 0) red[2] = nrm;
+        const double r0 = (j == 0) ? nrm : red[2];
+        if (!(nrm > tau * r0) || !(nrm > 0.0)) {
+          s_stop = j;
+        } else {
+          const double a = A[j + j * SM];
+          const double alpha = (a >= 0.0) ? -nrm : nrm;
+          const double vtv = 2.0 * nrm * (nrm + fabs(a));
+          red[0] = alpha;
+          red[1] = 2.0 / vtv;
+          A[j + j * SM] = a - alpha;
+        }
+      }
+    }
+    __syncthreads();
+    if (s_stop <= j) {
+      k = j;
+      break;
+    }
+    const double beta = red[1];
+    for (int l = j + 1 + wave; l < n; l += 4) {
+      double sdot = 0.0;
+      for (int i = j + lane; i < n; i += 64) sdot += A[i + j * SM] * A[i + l * SM];
+      for (int o = 32; o > 0; o >>= 1) sdot += __shfl_xor(sdot, o);
+      sdot *= beta;
+      for (int i = j + lane; i < n; i += 64) A[i + l * SM] -= sdot * A[i + j * SM];
+    }
+    __syncthreads();
+    if (tid == 0) A[j + j * SM] = red[0];
+    for (int l = j + 1 + tid; l < n; l += 256) {
+      const double r = A[j + l * SM];
+      double c = cn[l] - r * r;
+      if (!(c > 1e-8 * cn0[l])) {
+        c = 0.0;
+        for (int i = j + 1; i < n; ++i) c += A[i + l * SM] * A[i + l * SM];
+        cn0[l] = c;
+      }
+      cn[l] = c;
+    }
+    __syncthreads();
+  }
+  return k;
+}
+
+// Small dense problems built from upper-triangular R factors.
+//   SK_RECOMP   SVD of A = R1 R2^T = X S Y^T (one-sided Jacobi on A):
+//               CU = R2^T Y_k, CV = R1^T X_k S_k^{-1}, k = #{s > eps s_1}
+//   SK_SKETCH_P column-pivoted QR of R1 = R_Y (rank-revealing, stopped at
+//               tau): C1 = Pi_k R'_k^{-1}, so that Y C1 has orthonormal
+//               columns; the kept count is written as the rank
+//   SK_SKETCH_F SVD of A = R1 R2^{-1}: C1 = R2^{-1} Y_k, k = #{s > eps s_1}
+__global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, int* __restrict__ dyn,
                                                const SmallJob* __restrict__ jobs, int j0, int rmax,
                                                double eps_run, double tau_run, int* __restrict__ status) {
   const SmallJob J = jobs[j0 + blockIdx.x];
@@ -443,22 +612,43 @@ __global__ __launch_bounds__(256) void k_small(Bufs bufs, int* __restrict__ dyn,
   load_upper(refp(bufs, J.R1), rmax, n, R1);
   if (J.kind != SK_SKETCH_P) load_upper(refp(bufs, J.R2), rmax, n, R2);
   __syncthreads();
+  if (J.kind == SK_SKETCH_P) {
+    for (int e = tid; e < n * n; e += 256) {
+      int i = e % n, j = e / n;
+      A[i + j * SM] = (i <= j) ? R1[upk(i, j)] : 0.0;
+    }
+    __syncthreads();
+    // column norms in sv and in R2's (unused) storage; R'^{-1} into V
+    const int kk = qrcp_lds(A, n, eps, sv, R2, ord, red);
+    double* Xi = V;
+    for (int c = tid; c < kk; c += 256) {
+      for (int i = c; i >= 0; --i) {
+        double acc = (i == c) ? 1.0 : 0.0;
+        for (int l = i + 1; l <= c; ++l) acc -= A[i + l * SM] * Xi[l + c * SM];
+        Xi[i + c * SM] = acc / A[i + i * SM];
+      }
+    }
+    __syncthreads();
+    // C1 = Pi_k X: row ord[i] of C1 is row i of X; rows of dropped columns are 0
+    for (int e = tid; e < n * kk; e += 256) {
+      int i = e % n, c = e / n;
+      double v = (i <= c) ? Xi[i + c * SM] : 0.0;
+      if (i >= kk) v = 0.0;
+      C1[ord[i] + (size_t)c * rmax] = v;
+    }
+    if (tid == 0) dyn[J.out_rank_slot] = kk;
+    return;
+  }
   // ---- form the matrix to decompose
   if (J.kind == SK_RECOMP) {
-    // A = R1 R2^T (both upper triangular)
     for (int e = tid; e < n * n; e += 256) {
       int i = e % n, j = e / n;
       double acc = 0.0;
       for (int l = max(i, j); l < n; ++l) acc += R1[upk(i, l)] * R2[upk(j, l)];
       A[i + j * SM] = acc;
     }
-  } else if (J.kind == SK_SKETCH_P) {
-    for (int e = tid; e < n * n; e += 256) {
-      int i = e % n, j = e / n;
-      A[i + j * SM] = (i <= j) ? R1[upk(i, j)] : 0.0;
-    }
   } else {
-    // A = R1 R2^{-1}: row i solves g R2 = r1_i (R2 upper triangular)
+    // row i solves g R2 = r1_i (R2 upper triangular)
     for (int i = tid; i < n; i += 256) {
       for (int j = 0; j < n; ++j) {
         double acc = (i <= j) ? R1[upk(i, j)] : 0.0;
@@ -469,7 +659,11 @@ __global__ __launch_bounds__(256) void k_small(Bufs bufs, int* __restrict__ dyn,
     }
   }
   __syncthreads();
-  jacobi_svd_lds(A, V, n, red);
+  {
+    const double f2 = fro2_lds(A, n, red);
+    const double dt = 1e-3 * eps;
+    jacobi_svd_lds(A, V, n, dt * dt * f2, red);
+  }
   __syncthreads();
   order_desc(A, n, sv, ord);
   const double smax = sv[ord[0]];
@@ -502,15 +696,10 @@ __global__ __launch_bounds__(256) void k_small(Bufs bufs, int* __restrict__ dyn,
       C1[i + (size_t)c * rmax] = cu;
       C2[i + (size_t)c * rmax] = cv / (s * s);
     }
-  } else if (J.kind == SK_SKETCH_P) {
-    for (int e = tid; e < n * kk; e += 256) {
-      int i = e % n, c = e / n;
-      int oc = ord[c];
-      C1[i + (size_t)c * rmax] = V[i + oc * SM] / sv[oc];
-    }
   } else {
     // C = R2^{-1} Z_k, Z = V[:, ord]: back substitution, one thread per column,
     // the column kept in A's (now free) storage
+    __syncthreads();
     for (int c = tid; c < kk; c += 256) {
       int oc = ord[c];
       for (int i = n - 1; i >= 0; --i) {
@@ -530,127 +719,82 @@ __global__ __launch_bounds__(256) void k_small(Bufs bufs, int* __restrict__ dyn,
 }
 
 // ------------------------------------------------------------------ leaf
-// Dense leaf target: each thread owns an 8 x 8 block of the (<=128 x 128)
-// tile in registers; term factors are staged through LDS 16 columns at a
-// time.  Diagonal targets are then Cholesky-factorised in LDS.
-constexpr int LF = 128, LFK = 16;
+// Diagonal leaf factorisation (potrf, lower) of an updated tile of order
+// p <= 128.  Each thread owns an 8 x 8 block of the tile in registers (rows
+// ty + 16a with ty the lane index mod 16, so that loads coalesce; columns
+// tx + 16b).  Blocked right-looking Cholesky: each 16-column panel is copied
+// to LDS, factorised there column by column, copied back, and applied to the
+// trailing columns from registers.
+constexpr int LF = 128, LPW = 16, LPLD = LPW + 1;
 
-__global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__ dyn,
-                                              const LeafJob* __restrict__ jobs,
-                                              const LeafTerm* __restrict__ terms, int j0,
-                                              double* __restrict__ logdet, int* __restrict__ status) {
+__global__ __launch_bounds__(256) void k_leaf(const Bufs* __restrict__ bufs, const LeafJob* __restrict__ jobs,
+                                              int j0, double* __restrict__ logdet, int* __restrict__ status) {
   const LeafJob J = jobs[j0 + blockIdx.x];
   extern __shared__ double smem[];
-  double* Us = smem;                    // LFK x LF
-  double* Vs = smem + LFK * LF;         // LFK x LF
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double* Pn = smem;                  // LF x LPLD panel (row i at Pn[i * LPLD])
+  double* dg = smem + LF * LPLD;      // diagonal of the factor
+  const int tid = threadIdx.x, ty = tid & 15, tx = tid >> 4;
   double* __restrict__ Dp = refp(bufs, J.D);
-  const int ldd = J.D.ld, p = J.p, q = J.q;
+  const int ldd = J.D.ld, p = J.p;
   double acc[8][8];
 #pragma unroll
   for (int a = 0; a < 8; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
       int i = ty + 16 * a, j = tx + 16 * b;
-      acc[a][b] = (i < p && j < q) ? Dp[i + (size_t)j * ldd] : 0.0;
+      acc[a][b] = (i < p && j < p) ? Dp[i + (size_t)j * ldd] : 0.0;
     }
-  // term chunks of LFK columns: 16 values per thread, loaded into registers
-  // one chunk ahead of the FMAs that consume the chunk in LDS
-  auto load_chunk = [&](int t, int k0, double* ru, double* rv) {
-    const LeafTerm T = terms[t];
-    const int k = dimv(dyn, T.k);
-    const double* __restrict__ U = refp(bufs, T.U);
-    const double* __restrict__ V = refp(bufs, T.V);
+  int bad = -1;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      int e = tid + 256 * u;
-      int i = e & (LF - 1), kk = e >> 7;
-      int gk = k0 + kk;
-      int li = i - T.i0, lj = i - T.j0;
-      ru[u] = (li >= 0 && li < T.mi && gk < k) ? U[li + (size_t)gk * T.U.ld] : 0.0;
-      rv[u] = (lj >= 0 && lj < T.nj && gk < k) ? V[lj + (size_t)gk * T.V.ld] : 0.0;
-    }
-  };
-  // flatten (term, chunk) pairs
-  int t = J.t0, k0 = 0;
-  while (t < J.t1 && dimv(dyn, terms[t].k) <= 0) ++t;
-  double ru[8], rv[8];
-  if (t < J.t1) load_chunk(t, 0, ru, rv);
-  while (t < J.t1) {
-    __syncthreads();
+  for (int bb = 0; bb < LF / LPW; ++bb) {
+    const int jb = bb * LPW;
+    if (jb >= p || bad >= 0) break;
+    const int w = min(LPW, p - jb);
+    // panel columns jb..jb+w-1 (owned by the threads' column group bb) to LDS;
+    // rows above the panel are zero
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      int e = tid + 256 * u;
-      Us[e] = ru[u];   // e = kk * LF + i
-      Vs[e] = rv[u];
+    for (int a = 0; a < 8; ++a) {
+      int i = ty + 16 * a;
+      Pn[i * LPLD + tx] = (i >= jb && i < p) ? acc[a][bb] : 0.0;
     }
     __syncthreads();
-    // advance to the next chunk and prefetch it
-    int tn = t, kn = k0 + LFK;
-    if (kn >= dimv(dyn, terms[tn].k)) {
-      ++tn;
-      kn = 0;
-      while (tn < J.t1 && dimv(dyn, terms[tn].k) <= 0) ++tn;
-    }
-    if (tn < J.t1) load_chunk(tn, kn, ru, rv);
-#pragma unroll 4
-    for (int kk = 0; kk < LFK; ++kk) {
-      double a[8], b[8];
-#pragma unroll
-      for (int x = 0; x < 8; ++x) {
-        a[x] = Us[kk * LF + ty + 16 * x];
-        b[x] = Vs[kk * LF + tx + 16 * x];
+    // factorise the panel: thread r < p - jb owns row jb + r
+    const int i = jb + tid;
+    for (int c = 0; c < w; ++c) {
+      const double d = Pn[(jb + c) * LPLD + c];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = jb + c;
+        break;
       }
-#pragma unroll
-      for (int x = 0; x < 8; ++x)
-#pragma unroll
-        for (int y = 0; y < 8; ++y) acc[x][y] = fma(-a[x], b[y], acc[x][y]);
-    }
-    t = tn;
-    k0 = kn;
-  }
-  if (!J.diag) {
-#pragma unroll
-    for (int a = 0; a < 8; ++a)
-#pragma unroll
-      for (int b = 0; b < 8; ++b) {
-        int i = ty + 16 * a, j = tx + 16 * b;
-        if (i < p && j < q) Dp[i + (size_t)j * ldd] = acc[a][b];
-      }
-    return;
-  }
-  // potrf in LDS (lower), M col-major LF x LF
-  double* M = smem;   // reuse (LF*LF doubles = 128 KiB)
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      int i = ty + 16 * a, j = tx + 16 * b;
-      M[i + j * LF] = acc[a][b];
-    }
-  __shared__ int bad;
-  if (tid == 0) bad = -1;
-  __syncthreads();
-  for (int j = 0; j < p; ++j) {
-    double d = M[j + j * LF];
-    if (!(d > 0.0) || !isfinite(d)) {
-      if (tid == 0) bad = j;
+      const double ljj = sqrt(d);
+      __syncthreads();   // every thread has read d
+      if (i < p && i >= jb + c) Pn[i * LPLD + c] = (i == jb + c) ? ljj : Pn[i * LPLD + c] / ljj;
+      if (tid == 0) dg[jb + c] = ljj;
       __syncthreads();
-      break;
+      if (i < p && i > jb + c) {
+        const double lic = Pn[i * LPLD + c];
+        for (int c2 = c + 1; c2 < w && jb + c2 <= i; ++c2) Pn[i * LPLD + c2] -= lic * Pn[(jb + c2) * LPLD + c];
+      }
+      __syncthreads();
     }
-    const double ljj = sqrt(d);
-    const double inv = 1.0 / ljj;
-    // scale the column below the diagonal and update the trailing lower
-    // triangle: thread t owns row i = j+1+(t & 127) and every other column
-    const int i = j + 1 + (tid & 127);
-    const double lij = (i < p) ? M[i + j * LF] * inv : 0.0;
-    if (i < p)
-      for (int c = j + 1 + (tid >> 7); c <= i; c += 2) M[i + c * LF] -= lij * (M[c + j * LF] * inv);
-    __syncthreads();   // column j is read (unscaled) by every row above
-    if (i < p && (tid >> 7) == 0) M[i + j * LF] = lij;
-    if (tid == 0) M[j + j * LF] = ljj;
-    __syncthreads();
+    if (bad >= 0) break;
+    // factorised panel back to the owners; trailing update of later columns
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      int r = ty + 16 * a;
+      acc[a][bb] = (r >= jb + tx && r < p) ? Pn[r * LPLD + tx] : 0.0;
+    }
+#pragma unroll
+    for (int b = bb + 1; b < LF / LPW; ++b) {
+      if (b * 16 >= p) break;
+#pragma unroll 4
+      for (int c = 0; c < w; ++c) {
+        double lj = Pn[(tx + 16 * b) * LPLD + c];
+#pragma unroll
+        for (int a = 0; a < 8; ++a) acc[a][b] = fma(-Pn[(ty + 16 * a) * LPLD + c], lj, acc[a][b]);
+      }
+    }
+    __syncthreads();   // the panel buffer is rewritten by the next panel
   }
   if (bad >= 0) {
     if (tid == 0) {
@@ -660,13 +804,16 @@ __global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__
     }
     return;
   }
-  for (int e = tid; e < p * p; e += 256) {
-    int i = e % p, j = e / p;
-    Dp[i + (size_t)j * ldd] = (i >= j) ? M[i + j * LF] : 0.0;
-  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      int i = ty + 16 * a, j = tx + 16 * b;
+      if (i < p && j < p) Dp[i + (size_t)j * ldd] = (i >= j) ? acc[a][b] : 0.0;
+    }
   if (tid == 0) {
     double s = 0.0;
-    for (int j = 0; j < p; ++j) s += log(M[j + j * LF]);
+    for (int j = 0; j < p; ++j) s += log(dg[j]);
     logdet[J.leaf] = s;
   }
 }
@@ -679,7 +826,7 @@ __global__ __launch_bounds__(256) void k_leaf(Bufs bufs, const int* __restrict__
 // layout 0: X col-major (p x nc); layout 1: X^T stored (element (i,c) at
 // X[c + i*ld]); layout 2: solve L^T x = b.
 constexpr int TB = 16;
-__global__ __launch_bounds__(256) void k_trsm(Bufs bufs, const int* __restrict__ dyn,
+__global__ __launch_bounds__(256) void k_trsm(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
                                               const TrsmJob* __restrict__ jobs, int j0) {
   const TrsmJob J = jobs[j0 + blockIdx.x];
   const int nc = dimv(dyn, J.ncols);
@@ -1084,7 +1231,7 @@ __global__ void k_fill_value(double* __restrict__ out, int64_t n, double v) {
 
 constexpr size_t LDS_QR = (size_t(QR_LDS) + 8) * 8;
 constexpr size_t LDS_SMALL = (size_t(2) * SM * SM + size_t(SM) * (SM + 1) + SM + 8) * 8 + SM * 4;
-constexpr size_t LDS_LEAF = size_t(LF) * LF * 8;
+constexpr size_t LDS_LEAF = size_t(LF * LPLD + LF) * 8;
 constexpr size_t LDS_TRSM = (size_t(LF) * (LF + 1) / 2 + size_t(LF) * 64) * 8;
 
 hipError_t setup_kernel_attributes() {
@@ -1105,23 +1252,23 @@ hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st) {
   const int n = s.end - s.begin;
   switch (s.kind) {
     case ST_GEMM:
-      if (n > 0) k_gemm<<<n, 256, 0, st>>>(L.bufs, L.dyn, L.gjobs, L.gprods, L.gtiles, s.begin);
+      if (n > 0) k_gemm<<<n, 256, 0, st>>>(L.dbufs, L.dyn, L.gjobs, L.gprods, L.gtiles, s.begin);
       break;
     case ST_TSQR_SEG:
-      if (n > 0) k_tsqr_seg<<<n, 256, LDS_QR, st>>>(L.bufs, L.dyn, L.tsegs, s.begin, L.rmax);
+      if (n > 0) k_tsqr_seg<<<n, 256, LDS_QR, st>>>(L.dbufs, L.dyn, L.tsegs, s.begin, L.rmax);
       break;
     case ST_TSQR_RED:
-      if (n > 0) k_tsqr_red<<<n, 256, LDS_QR, st>>>(L.bufs, L.dyn, L.treds, s.begin, L.rmax);
+      if (n > 0) k_tsqr_red<<<n, 256, LDS_QR, st>>>(L.dbufs, L.dyn, L.treds, s.begin, L.rmax);
       break;
     case ST_SMALL:
       if (n > 0)
-        k_small<<<n, 256, LDS_SMALL, st>>>(L.bufs, L.dyn, L.smalls, s.begin, L.rmax, L.eps, L.tau, L.status);
+        k_small<<<n, 256, LDS_SMALL, st>>>(L.dbufs, L.dyn, L.smalls, s.begin, L.rmax, L.eps, L.tau, L.status);
       break;
     case ST_LEAF:
-      if (n > 0) k_leaf<<<n, 256, LDS_LEAF, st>>>(L.bufs, L.dyn, L.leafs, L.lterms, s.begin, L.logdet, L.status);
+      if (n > 0) k_leaf<<<n, 256, LDS_LEAF, st>>>(L.dbufs, L.leafs, s.begin, L.logdet, L.status);
       break;
     case ST_TRSM:
-      if (n > 0) k_trsm<<<n, 256, LDS_TRSM, st>>>(L.bufs, L.dyn, L.trsms, s.begin);
+      if (n > 0) k_trsm<<<n, 256, LDS_TRSM, st>>>(L.dbufs, L.dyn, L.trsms, s.begin);
       break;
     case ST_COPY_RANK:
       if (L.n_copy > 0) k_copy_rank<<<(L.n_copy + 255) / 256, 256, 0, st>>>(L.dyn, L.copy_pairs, L.n_copy);

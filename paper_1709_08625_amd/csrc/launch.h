@@ -25,7 +25,8 @@ struct AcaJob {
 
 // Device copies of the plan arrays and the run-time state a stage needs.
 struct LaunchCtx {
-  Bufs bufs;
+  Bufs bufs;            // host copy of the buffer table
+  const Bufs* dbufs;    // the same table in device memory (kernels read it)
   int* dyn;
   const GemmJob* gjobs;
   const GemmProd* gprods;
@@ -34,7 +35,6 @@ struct LaunchCtx {
   const TsqrRed* treds;
   const SmallJob* smalls;
   const LeafJob* leafs;
-  const LeafTerm* lterms;
   const TrsmJob* trsms;
   const int2* copy_pairs;
   int n_copy;

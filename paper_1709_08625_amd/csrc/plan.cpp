@@ -22,11 +22,14 @@
 #include <cassert>
 #include <cstdio>
 #include <functional>
+#include <map>
+#include <tuple>
 
 namespace hc {
 
 static const int TM = 64, TN = 64;   // GEMM tile (must match the kernel)
-static const int TSQR_SEG = 1024;    // rows per TSQR segment work-group
+static const int TSQR_SEG = 384;     // rows per TSQR segment work-group
+static const int TSQR_FAN = 16;      // R factors per TSQR reduction work-group
 static const int LEAF_MAX = 128;
 
 int64_t node_lo(const Plan& P, int l, int64_t i) { return P.lo[l][i]; }
@@ -68,6 +71,63 @@ class Builder {
     int32_t s = dyn_top++;
     if (dyn_top > dyn_max) dyn_max = dyn_top;
     return s;
+  }
+
+  // Cached rank x rank cores V_A[K]^T V_B[K] of pairs of low-rank blocks of
+  // the factor.  Once the sweep has passed the last leaf of K both panels are
+  // final, so every later target that needs the product of the same two
+  // blocks over the same K reuses one core in the persistent scratch.  A core
+  // is needed only by targets whose column lies in the row cluster of B, so
+  // its slot is recycled after the last leaf of that cluster.
+  struct CoreKey {
+    int32_t a, b;
+    int64_t k0, k1;
+    bool operator<(const CoreKey& o) const {
+      return std::tie(a, b, k0, k1) < std::tie(o.a, o.b, o.k0, o.k1);
+    }
+  };
+  std::map<CoreKey, int64_t> core_slot;
+  std::vector<int64_t> core_free;
+  std::vector<std::vector<std::pair<CoreKey, int64_t>>> core_release;   // by step
+  int64_t core_base = 0, core_top = 0, cur_step = 0;
+
+  void core_reset(int64_t steps) {
+    core_slot.clear();
+    core_free.clear();
+    core_release.assign(steps + 1, {});
+    core_top = core_base;
+  }
+  void core_step(int64_t j) {
+    cur_step = j;
+    for (auto& e : core_release[j]) {
+      core_slot.erase(e.first);
+      core_free.push_back(e.second);
+    }
+    core_release[j].clear();
+  }
+  // returns the slot offset; *fresh tells the caller to compute it
+  int64_t core_get(int32_t a, int32_t b, int64_t k0, int64_t k1, bool* fresh) {
+    CoreKey key{a, b, k0, k1};
+    auto it = core_slot.find(key);
+    if (it != core_slot.end()) {
+      *fresh = false;
+      return it->second;
+    }
+    *fresh = true;
+    int64_t o;
+    if (!core_free.empty()) {
+      o = core_free.back();
+      core_free.pop_back();
+    } else {
+      o = core_top;
+      core_top += int64_t(P.kcap) * P.kcap;
+      if (core_top > P.pers_elems) P.pers_elems = core_top;
+    }
+    core_slot[key] = o;
+    const BlockInfo& B = P.blocks[b];
+    int64_t last = ((int64_t(B.a) + 1) << (P.D - B.level)) - 1;   // last leaf of rows(B)
+    core_release[std::max<int64_t>(last + 1, cur_step + 1)].push_back({key, o});
+    return o;
   }
 
   // ---------------------------------------------------------------- GEMM
@@ -131,10 +191,13 @@ class Builder {
   };
   std::vector<TsqrReq> tsqr_pending;
   void tsqr(Ref X, int64_t rows, Dim cols, Ref R) { tsqr_pending.push_back(TsqrReq{X, rows, cols, R}); }
+  // Segment R factors are combined by a tree of reductions of at most
+  // TSQR_FAN factors each; every tree level is one launch.
   void flush_tsqr(std::vector<Stage>& out) {
     if (tsqr_pending.empty()) return;
-    int32_t s0 = int32_t(P.tsegs.size()), r0 = int32_t(P.treds.size());
+    int32_t s0 = int32_t(P.tsegs.size());
     const int64_t RR = int64_t(P.rmax) * P.rmax;
+    std::vector<std::vector<TsqrRed>> levels;
     for (auto& q : tsqr_pending) {
       int64_t nseg = (q.rows + TSQR_SEG - 1) / TSQR_SEG;
       if (nseg <= 1) {
@@ -148,12 +211,32 @@ class Builder {
         int32_t rows = int32_t(std::min<int64_t>(TSQR_SEG, q.rows - s * TSQR_SEG));
         P.tsegs.push_back(TsqrSeg{X, rows, q.cols, Ref{B_SCR, P.rmax, base + s * RR}});
       }
-      P.treds.push_back(TsqrRed{Ref{B_SCR, P.rmax, base}, int32_t(nseg), q.cols, q.R});
+      int64_t cnt = nseg;
+      size_t lv = 0;
+      while (cnt > TSQR_FAN) {
+        int64_t ng = (cnt + TSQR_FAN - 1) / TSQR_FAN;
+        int64_t nb = scr_alloc(ng * RR);
+        if (levels.size() <= lv) levels.resize(lv + 1);
+        for (int64_t g = 0; g < ng; ++g)
+          levels[lv].push_back(TsqrRed{Ref{B_SCR, P.rmax, base + g * TSQR_FAN * RR},
+                                       int32_t(std::min<int64_t>(TSQR_FAN, cnt - g * TSQR_FAN)), q.cols,
+                                       Ref{B_SCR, P.rmax, nb + g * RR}});
+        base = nb;
+        cnt = ng;
+        ++lv;
+      }
+      if (levels.size() <= lv) levels.resize(lv + 1);
+      levels[lv].push_back(TsqrRed{Ref{B_SCR, P.rmax, base}, int32_t(cnt), q.cols, q.R});
     }
     tsqr_pending.clear();
-    int32_t s1 = int32_t(P.tsegs.size()), r1 = int32_t(P.treds.size());
+    int32_t s1 = int32_t(P.tsegs.size());
     if (s1 > s0) out.push_back(Stage{ST_TSQR_SEG, s0, s1});
-    if (r1 > r0) out.push_back(Stage{ST_TSQR_RED, r0, r1});
+    for (auto& L : levels) {
+      if (L.empty()) continue;
+      int32_t r0 = int32_t(P.treds.size());
+      for (auto& r : L) P.treds.push_back(r);
+      out.push_back(Stage{ST_TSQR_RED, r0, int32_t(P.treds.size())});
+    }
   }
 
   void flush_small(std::vector<Stage>& out, int32_t s0) {
@@ -245,41 +328,94 @@ class Builder {
     p.alpha = alpha;
     d.prods.push_back(p);
   }
-  // Emit deferred jobs as one GEMM stage.  Products with a static inner
-  // dimension above KSPLIT are split into chunks that write partial sums to
-  // scratch; a second stage adds the partials into the real output in a
-  // fixed order (deterministic, no atomics).
-  static constexpr int KSPLIT = 2048;
+  // Emit deferred jobs as one GEMM stage.  A work-group streams the k
+  // chunks of every product of its job that meets its tile, so a job whose
+  // busiest tile would stream more than TILE_BUDGET chunks is split: long
+  // static-k products are cut into k ranges, and the pieces are packed
+  // first-fit into groups whose per-tile cost fits the budget.  Each group
+  // writes a partial sum to scratch and a second stage adds the partials
+  // into the real output in a fixed order (deterministic, no atomics).
+  static constexpr int GKP = 32;            // k chunk of the GEMM kernel
+  static constexpr int TILE_BUDGET = 16;    // k chunks per tile and launch
+  static constexpr int64_t PART_CAP = int64_t(1) << 23;   // scratch elements per split job
+  static int est_k(const Dim& k) { return k.slot < 0 ? k.maxv : std::min(k.maxv, 32); }
+  static int chunks(int k) { return (k + GKP - 1) / GKP; }
   void emit(std::vector<Deferred>& L, std::vector<Stage>& out) {
     std::vector<Deferred> finals;
     for (auto& d : L) {
-      int nsplit = 1;
-      for (auto& p : d.prods)
-        if (p.k.slot < 0 && p.tb != 2 && p.k.maxv > KSPLIT) nsplit = std::max(nsplit, (p.k.maxv + KSPLIT - 1) / KSPLIT);
-      if (nsplit == 1) {
+      const int mcap = d.m.maxv, ncap = d.n.maxv;
+      const int tr = (mcap + 63) / 64, tc = (ncap + 63) / 64;
+      // tile range of a product (capacity-based)
+      auto span = [&](const GemmProd& p, int& a0, int& a1, int& b0, int& b1) {
+        a0 = p.i0 / 64;
+        a1 = std::min(tr, (p.i0 + p.mi.maxv + 63) / 64);
+        b0 = p.j0 / 64;
+        b1 = std::min(tc, (p.j0 + p.nj.maxv + 63) / 64);
+      };
+      // busiest tile of the unsplit job
+      std::vector<int> cost(size_t(tr) * tc, 0);
+      int worst = 0;
+      for (auto& p : d.prods) {
+        int a0, a1, b0, b1;
+        span(p, a0, a1, b0, b1);
+        int c = p.tb == 2 ? 1 : chunks(est_k(p.k));
+        for (int x = a0; x < a1; ++x)
+          for (int y = b0; y < b1; ++y) worst = std::max(worst, cost[size_t(x) * tc + y] += c);
+      }
+      std::vector<std::vector<GemmProd>> groups;
+      if (worst > TILE_BUDGET && int64_t(mcap) * ncap * 2 <= PART_CAP) {
+        // pieces: long static-k products cut into k ranges of the budget
+        std::vector<GemmProd> pieces;
+        const int kcut = TILE_BUDGET * GKP;
+        for (auto& p : d.prods) {
+          if (p.k.slot >= 0 || p.tb == 2 || p.k.maxv <= kcut) {
+            pieces.push_back(p);
+            continue;
+          }
+          for (int k0 = 0; k0 < p.k.maxv; k0 += kcut) {
+            GemmProd q = p;
+            q.k = dim_static(std::min(kcut, p.k.maxv - k0));
+            q.A.off += (p.ta == 0) ? int64_t(k0) * p.A.ld : int64_t(k0);
+            q.B.off += (p.tb == 0) ? int64_t(k0) : int64_t(k0) * p.B.ld;
+            pieces.push_back(q);
+          }
+        }
+        std::vector<std::vector<int>> gcost;
+        const int64_t gmax = std::max<int64_t>(2, PART_CAP / (int64_t(mcap) * ncap));
+        for (auto& q : pieces) {
+          int a0, a1, b0, b1;
+          span(q, a0, a1, b0, b1);
+          int c = q.tb == 2 ? 1 : chunks(est_k(q.k));
+          size_t g = 0;
+          for (; g < groups.size(); ++g) {
+            bool fits = true;
+            for (int x = a0; x < a1 && fits; ++x)
+              for (int y = b0; y < b1 && fits; ++y) fits = gcost[g][size_t(x) * tc + y] + c <= TILE_BUDGET;
+            if (fits) break;
+          }
+          if (g == groups.size()) {
+            if (int64_t(groups.size()) >= gmax) {
+              g = groups.size() - 1;   // scratch cap: overload the last group
+            } else {
+              groups.emplace_back();
+              gcost.emplace_back(size_t(tr) * tc, 0);
+            }
+          }
+          groups[g].push_back(q);
+          for (int x = a0; x < a1; ++x)
+            for (int y = b0; y < b1; ++y) gcost[g][size_t(x) * tc + y] += c;
+        }
+      }
+      if (groups.size() <= 1) {
         int32_t j = gemm_job(d.C, d.m, d.n, d.zero);
         for (auto& p : d.prods) add_prod(j, p.A, p.ta, p.B, p.tb, p.k, p.i0, p.j0, p.mi, p.nj, p.alpha);
         continue;
       }
-      const int mcap = d.m.maxv, ncap = d.n.maxv;
       Deferred fin{d.C, d.m, d.n, d.zero, {}};
-      for (int sp = 0; sp < nsplit; ++sp) {
+      for (auto& g : groups) {
         int64_t pb = scr_alloc(int64_t(mcap) * ncap);
         int32_t j = gemm_job(Ref{B_SCR, mcap, pb}, d.m, d.n, 1);
-        for (auto& p : d.prods) {
-          bool splittable = p.k.slot < 0 && p.tb != 2 && p.k.maxv > KSPLIT;
-          if (!splittable) {
-            if (sp == 0) add_prod(j, p.A, p.ta, p.B, p.tb, p.k, p.i0, p.j0, p.mi, p.nj, p.alpha);
-            continue;
-          }
-          int k0 = sp * KSPLIT;
-          if (k0 >= p.k.maxv) continue;
-          int kc = std::min(KSPLIT, p.k.maxv - k0);
-          Ref A = p.A, B = p.B;
-          A.off += (p.ta == 0) ? int64_t(k0) * A.ld : int64_t(k0);
-          B.off += (p.tb == 0) ? int64_t(k0) : int64_t(k0) * B.ld;
-          add_prod(j, A, p.ta, B, p.tb, dim_static(kc), p.i0, p.j0, p.mi, p.nj, p.alpha);
-        }
+        for (auto& p : g) add_prod(j, p.A, p.ta, p.B, p.tb, p.k, p.i0, p.j0, p.mi, p.nj, p.alpha);
         dprod(fin, Ref{B_SCR, mcap, pb}, 0, Ref{B_SCR, mcap, pb}, 2, dim_static(1), 0, 0, d.m, d.n, 1.0);
       }
       finals.push_back(fin);
@@ -340,7 +476,19 @@ class Builder {
     int nr = int(r1 - r0), nc = int(c1 - c0);
     if (nr <= 0 || nc <= 0) return;
     if (!transpose) {
-      if (B.kind == 1) {
+      if (B.kind == 1 && xblk >= 0) {
+        // X is the final V panel of block xblk: T^T = V_xblk[c]^T V_b[c] is a cached core
+        bool fresh = false;
+        int64_t c = core_get(xblk, b, c0, c1, &fresh);
+        if (fresh) {
+          int32_t dA = defer(LA, Ref{B_PERS, P.kcap, c}, X.cols, rank_dim(b), 1);
+          Ref Xr = X.ref;
+          Xr.off += (c0 - xcol0);
+          dprod(LA[dA], Xr, 1, lr_v(b, c0).ref, 0, dim_static(nc), 0, 0, X.cols, rank_dim(b), 1.0);
+        }
+        dprod(LB[dB], lr_u(b, r0).ref, 0, Ref{B_PERS, P.kcap, c}, 1, rank_dim(b), int(r0 - wrow0),
+              0, dim_static(nr), X.cols, alpha);
+      } else if (B.kind == 1) {
         // T = V_b[c]^T X[c]  (rank x X.cols)
         Src V = lr_v(b, c0);
         int64_t t = scr_alloc(int64_t(P.kcap) * X.cols.maxv);
@@ -379,6 +527,10 @@ class Builder {
     }
   }
 
+  // block whose final V panel is the right-hand side of the current H-matvec
+  // (enables the core cache in piece()), or -1
+  int32_t xblk = -1;
+
   // H-matvec producing a fresh scratch W = L(P,K) X
   Src hmatvec(int l, int64_t p, int lk, int64_t k, const Src& X, int64_t xcol0) {
     int64_t P0 = lo(l, p), P1 = hi(l, p);
@@ -402,26 +554,33 @@ class Builder {
       if (kP == 1) {
         // U_t = Ua[R] (Va[K]^T Vb[K]),  V_t = Ub[P]
         Src Vb = lr_v(sP, K0);
-        int64_t c = scr_alloc(int64_t(P.kcap) * P.kcap);
-        int32_t dA = defer(listA, Ref{B_SCR, P.kcap, c}, rank_dim(sR), rank_dim(sP), 1);
-        dprod(listA[dA], Va.ref, 1, Vb.ref, 0, dim_static(int(K1 - K0)), 0, 0, rank_dim(sR),
-              rank_dim(sP), 1.0);
+        bool fresh = false;
+        int64_t c = core_get(sR, sP, K0, K1, &fresh);
+        if (fresh) {
+          int32_t dA = defer(listA, Ref{B_PERS, P.kcap, c}, rank_dim(sR), rank_dim(sP), 1);
+          dprod(listA[dA], Va.ref, 1, Vb.ref, 0, dim_static(int(K1 - K0)), 0, 0, rank_dim(sR),
+                rank_dim(sP), 1.0);
+        }
         int64_t u = scr_alloc((R1 - R0) * int64_t(P.kcap));
         int32_t dB = defer(listB, Ref{B_SCR, int32_t(R1 - R0), u}, dim_static(int(R1 - R0)),
                            rank_dim(sP), 1);
-        dprod(listB[dB], Ua.ref, 0, Ref{B_SCR, P.kcap, c}, 0, rank_dim(sR), 0, 0,
+        dprod(listB[dB], Ua.ref, 0, Ref{B_PERS, P.kcap, c}, 0, rank_dim(sR), 0, 0,
               dim_static(int(R1 - R0)), rank_dim(sP), 1.0);
         out.push_back(Term{R0, R1, Q0, Q1, Src{Ref{B_SCR, int32_t(R1 - R0), u}, rank_dim(sP)},
                            lr_u(sP, Q0)});
       } else {
+        xblk = sR;
         Src W = hmatvec(l, p, lk, k, Va, K0);
+        xblk = -1;
         out.push_back(Term{R0, R1, Q0, Q1, Ua, W});
       }
       return;
     }
     if (kP == 1) {
       Src Vb = lr_v(sP, K0);
+      xblk = sP;
       Src W = hmatvec(l, a, lk, k, Vb, K0);
+      xblk = -1;
       out.push_back(Term{R0, R1, Q0, Q1, W, lr_u(sP, Q0)});
       return;
     }
@@ -482,10 +641,12 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
     by_col[key3(B.level, B.c, 0)].push_back(b);
   }
   steps.assign(m, {});
+  core_reset(m);
   const int RM = P.rmax;
   const int64_t RR = int64_t(RM) * RM;
   for (int64_t j = 0; j < m; ++j) {
     std::vector<Stage>& st = steps[j];
+    core_step(j);
     scr_top = 0;
     dyn_top = dyn_base;
     const int64_t cj0 = lo(D, j), cj1 = hi(D, j);
@@ -508,6 +669,20 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
     }
     emit(listA, st);   // inner products and cores
     emit(listB, st);   // W accumulation and U*core
+
+    // ---- dense targets: D -= sum of the update terms, as GEMM jobs on the
+    // target tile (split into partial sums by emit() when long); they go into
+    // the same launch as the first sketch products
+    for (auto& dt : dns) {
+      if (dt.second.empty()) continue;
+      const BlockInfo& B = P.blocks[dt.first];
+      const int p = int(B.r1 - B.r0), q = int(B.c1 - B.c0);
+      int32_t d = defer(listA, Ref{B_DENSE, p, B.off_d}, dim_static(p), dim_static(q), 0);
+      for (auto& T : dt.second)
+        dprod(listA[d], T.U.ref, 0, T.V.ref, 1, T.U.cols, int(T.r0 - B.r0), int(T.p0 - B.c0),
+              dim_static(int(T.r1 - T.r0)), dim_static(int(T.p1 - T.p0)), -1.0);
+    }
+    if (lrs.empty()) emit(listA, st);
 
     // ---- randomised recompression of low-rank targets
     if (!lrs.empty()) {
@@ -665,35 +840,18 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
       emit(listA, st);
     }
 
-    // ---- dense targets (incl. the diagonal leaf): update, potrf
+    // ---- diagonal leaf: potrf (its update was applied by the GEMM stage)
     {
+      const int32_t db = P.diag_block[j];
+      const BlockInfo& B = P.blocks[db];
+      LeafJob J{};
+      J.D = Ref{B_DENSE, int32_t(B.r1 - B.r0), B.off_d};
+      J.p = int32_t(B.r1 - B.r0);
+      J.leaf = int32_t(j);
+      J.row0 = B.r0;
       int32_t l0 = int32_t(P.leafs.size());
-      for (auto& dt : dns) {
-        const BlockInfo& B = P.blocks[dt.first];
-        LeafJob J{};
-        J.D = Ref{B_DENSE, int32_t(B.r1 - B.r0), B.off_d};
-        J.p = int32_t(B.r1 - B.r0);
-        J.q = int32_t(B.c1 - B.c0);
-        J.diag = (B.a == B.c) ? 1 : 0;
-        J.leaf = int32_t(j);
-        J.row0 = B.r0;
-        J.t0 = int32_t(P.lterms.size());
-        for (auto& T : dt.second) {
-          LeafTerm L{};
-          L.U = T.U.ref;
-          L.V = T.V.ref;
-          L.k = T.U.cols;
-          L.i0 = int32_t(T.r0 - B.r0);
-          L.j0 = int32_t(T.p0 - B.c0);
-          L.mi = int32_t(T.r1 - T.r0);
-          L.nj = int32_t(T.p1 - T.p0);
-          P.lterms.push_back(L);
-        }
-        J.t1 = int32_t(P.lterms.size());
-        P.leafs.push_back(J);
-      }
-      int32_t l1 = int32_t(P.leafs.size());
-      if (l1 > l0) st.push_back(Stage{ST_LEAF, l0, l1});
+      P.leafs.push_back(J);
+      st.push_back(Stage{ST_LEAF, l0, l0 + 1});
     }
 
     // ---- triangular solves with L_jj
@@ -744,7 +902,9 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
           if (it == by_col.end()) continue;
           for (int32_t b : it->second) {
             const BlockInfo& B = P.blocks[b];
+            xblk = b;
             rhs(Ref{B_V, int32_t(B.c1 - B.c0), B.off_v}, B.c0, rank_dim(b));
+            xblk = -1;
           }
         }
         if (fuse_rhs) rhs(Ref{B_RHS, int32_t(P.rhs_ld), 0}, 0, dim_static(1));
@@ -1051,6 +1211,7 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
   Bd.dyn_max = dyn;
   P.n_dyn = dyn;
   Bd.build_recompress();
+  Bd.core_base = P.pers_elems;   // cores live above the assembly R slots
   Bd.build_steps(true, P.steps);
   Bd.build_steps(false, P.steps_nofuse);
   Bd.build_solves();

@@ -106,23 +106,13 @@ struct SmallJob {
 };
 
 // ---------------------------------------------------------------- leaf jobs
-// Dense leaf target (p, q <= LEAF_MAX): M = D - sum_t U_t V_t^T, written
-// back to D; for diagonal blocks M is then factorised in place (potrf) and
-// sum log L_ii is stored to logdet[leaf].
+// Diagonal leaf (p <= LEAF_MAX), already updated: factorised in place
+// (potrf, lower) and sum log L_ii is stored to logdet[leaf].
 struct LeafJob {
   Ref D;
-  int32_t p, q;
-  int32_t diag;     // 1: potrf
-  int32_t leaf;     // leaf index (diag) for logdet / error reporting
-  int32_t t0, t1;   // terms [t0, t1) in the LeafTerm array
+  int32_t p;
+  int32_t leaf;     // leaf index for logdet / error reporting
   int64_t row0;     // global cluster-order index of the first row (errors)
-};
-struct LeafTerm {
-  Ref U;  // rows x k (col-major, ld)
-  Ref V;  // cols x k
-  Dim k;
-  int32_t i0, j0;   // placement inside the target
-  int32_t mi, nj;   // extent
 };
 
 // ---------------------------------------------------------------- trsm jobs
@@ -175,7 +165,6 @@ struct Plan {
   std::vector<TsqrRed> treds;
   std::vector<SmallJob> smalls;
   std::vector<LeafJob> leafs;
-  std::vector<LeafTerm> lterms;
   std::vector<TrsmJob> trsms;
 
   // schedules

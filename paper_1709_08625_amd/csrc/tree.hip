@@ -213,18 +213,18 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
   // global ranks along x and y
   unsigned long long *kin = nullptr, *kout = nullptr;
   int *vin = nullptr, *vout = nullptr, *rx = nullptr, *ry = nullptr, *perm = nullptr;
-  TCHK(hipMalloc(&kin, n * 8));
-  TCHK(hipMalloc(&kout, n * 8));
-  TCHK(hipMalloc(&vin, n * 4));
-  TCHK(hipMalloc(&vout, n * 4));
-  TCHK(hipMalloc(&rx, n * 4));
-  TCHK(hipMalloc(&ry, n * 4));
-  TCHK(hipMalloc(&perm, n * 4));
+  TCHK(hipMallocAsync(&kin, n * 8, st));
+  TCHK(hipMallocAsync(&kout, n * 8, st));
+  TCHK(hipMallocAsync(&vin, n * 4, st));
+  TCHK(hipMallocAsync(&vout, n * 4, st));
+  TCHK(hipMallocAsync(&rx, n * 4, st));
+  TCHK(hipMallocAsync(&ry, n * 4, st));
+  TCHK(hipMallocAsync(&perm, n * 4, st));
   void* tmp = nullptr;
   size_t tmpb = 0, need = 0;
   TCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)n, 0, 64, st));
   tmpb = need;
-  TCHK(hipMalloc(&tmp, tmpb + 256));
+  TCHK(hipMallocAsync(&tmp, tmpb + 256, st));
   for (int ax = 0; ax < 2; ++ax) {
     k_axis_keys<<<nblk(n, 256), 256, 0, st>>>(loc, n, ax, kin, vin);
     TCHK(hipGetLastError());
@@ -242,13 +242,13 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
   }
   int64_t total_nodes = (int64_t(2) << D) - 1;
   double* bbox_all = nullptr;
-  TCHK(hipMalloc(&bbox_all, total_nodes * 4 * 8));
+  TCHK(hipMallocAsync(&bbox_all, total_nodes * 4 * 8, st));
   unsigned long long* bbk = nullptr;
   signed char* axis = nullptr;
   int64_t* dlo = nullptr;
-  TCHK(hipMalloc(&bbk, ((int64_t)1 << D) * 4 * 8));
-  TCHK(hipMalloc(&axis, ((int64_t)1 << D)));
-  TCHK(hipMalloc(&dlo, (((int64_t)1 << D) + 1) * 8));
+  TCHK(hipMallocAsync(&bbk, ((int64_t)1 << D) * 4 * 8, st));
+  TCHK(hipMallocAsync(&axis, ((int64_t)1 << D), st));
+  TCHK(hipMallocAsync(&dlo, (((int64_t)1 << D) + 1) * 8, st));
   for (int l = 0; l <= D; ++l) {
     int cnt = 1 << l;
     TCHK(hipMemcpyAsync(dlo, lo[l].data(), (cnt + 1) * 8, hipMemcpyHostToDevice, st));
@@ -291,19 +291,19 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
     if (c <= wk_cap) return "";
     int64_t nc = std::max<int64_t>(1024, wk_cap);
     while (nc < c) nc *= 2;
-    if (nx) TCHK(hipFree(nx));
-    if (isl) TCHK(hipFree(isl));
-    if (nch) TCHK(hipFree(nch));
-    if (knd) TCHK(hipFree(knd));
-    if (lpos) TCHK(hipFree(lpos));
-    if (cpos) TCHK(hipFree(cpos));
+    if (nx) TCHK(hipFreeAsync(nx, st));
+    if (isl) TCHK(hipFreeAsync(isl, st));
+    if (nch) TCHK(hipFreeAsync(nch, st));
+    if (knd) TCHK(hipFreeAsync(knd, st));
+    if (lpos) TCHK(hipFreeAsync(lpos, st));
+    if (cpos) TCHK(hipFreeAsync(cpos, st));
     wk_cap = nc;
-    TCHK(hipMalloc(&nx, (wk_cap * 4) * 8));
-    TCHK(hipMalloc(&isl, (wk_cap + 1) * 4));
-    TCHK(hipMalloc(&nch, (wk_cap + 1) * 4));
-    TCHK(hipMalloc(&knd, (wk_cap + 1) * 4));
-    TCHK(hipMalloc(&lpos, (wk_cap + 1) * 4));
-    TCHK(hipMalloc(&cpos, (wk_cap + 1) * 4));
+    TCHK(hipMallocAsync(&nx, (wk_cap * 4) * 8, st));
+    TCHK(hipMallocAsync(&isl, (wk_cap + 1) * 4, st));
+    TCHK(hipMallocAsync(&nch, (wk_cap + 1) * 4, st));
+    TCHK(hipMallocAsync(&knd, (wk_cap + 1) * 4, st));
+    TCHK(hipMallocAsync(&lpos, (wk_cap + 1) * 4, st));
+    TCHK(hipMallocAsync(&cpos, (wk_cap + 1) * 4, st));
     return "";
   };
   // frontier array (contents not preserved: it is rewritten from nx)
@@ -311,16 +311,16 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
     if (c <= fr_cap) return "";
     int64_t nc = std::max<int64_t>(1024, fr_cap);
     while (nc < c) nc *= 2;
-    if (fr) TCHK(hipFree(fr));
+    if (fr) TCHK(hipFreeAsync(fr, st));
     fr_cap = nc;
-    TCHK(hipMalloc(&fr, fr_cap * 8));
+    TCHK(hipMallocAsync(&fr, fr_cap * 8, st));
     return "";
   };
   {
     std::string g = ensure_fr(1);
     if (!g.empty()) return g;
   }
-  TCHK(hipMalloc(&leaves, leaf_cap * 16));
+  TCHK(hipMallocAsync(&leaves, leaf_cap * 16, st));
   {
     int2 root = make_int2(0, 0);
     TCHK(hipMemcpyAsync(fr, &root, 8, hipMemcpyHostToDevice, st));
@@ -337,9 +337,9 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
     size_t need2 = 0;
     TCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, need2, isl, lpos, (int)cnt + 1, st));
     if (need2 > stmpb) {
-      if (stmp) TCHK(hipFree(stmp));
+      if (stmp) TCHK(hipFreeAsync(stmp, st));
       stmpb = need2 * 2;
-      TCHK(hipMalloc(&stmp, stmpb));
+      TCHK(hipMallocAsync(&stmp, stmpb, st));
     }
     TCHK(hipMemsetAsync(isl + cnt, 0, 4, st));
     TCHK(hipMemsetAsync(nch + cnt, 0, 4, st));
@@ -355,10 +355,10 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
       int64_t nc = leaf_cap;
       while (nc < nleaves + tot[0]) nc *= 2;
       int4* l2 = nullptr;
-      TCHK(hipMalloc(&l2, nc * 16));
+      TCHK(hipMallocAsync(&l2, nc * 16, st));
       TCHK(hipMemcpyAsync(l2, leaves, nleaves * 16, hipMemcpyDeviceToDevice, st));
       TCHK(hipStreamSynchronize(st));
-      TCHK(hipFree(leaves));
+      TCHK(hipFreeAsync(leaves, st));
       leaves = l2;
       leaf_cap = nc;
     }
@@ -385,26 +385,26 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
     out.blocks[4 * i + 2] = lh[i].z;
     out.blocks[4 * i + 3] = lh[i].w;
   }
-  hipFree(fr);
-  hipFree(nx);
-  hipFree(isl);
-  hipFree(nch);
-  hipFree(knd);
-  hipFree(lpos);
-  hipFree(cpos);
-  hipFree(leaves);
-  if (stmp) hipFree(stmp);
-  hipFree(kin);
-  hipFree(kout);
-  hipFree(vin);
-  hipFree(vout);
-  hipFree(rx);
-  hipFree(ry);
-  hipFree(tmp);
-  hipFree(bbox_all);
-  hipFree(bbk);
-  hipFree(axis);
-  hipFree(dlo);
+  hipFreeAsync(fr, st);
+  hipFreeAsync(nx, st);
+  hipFreeAsync(isl, st);
+  hipFreeAsync(nch, st);
+  hipFreeAsync(knd, st);
+  hipFreeAsync(lpos, st);
+  hipFreeAsync(cpos, st);
+  hipFreeAsync(leaves, st);
+  if (stmp) hipFreeAsync(stmp, st);
+  hipFreeAsync(kin, st);
+  hipFreeAsync(kout, st);
+  hipFreeAsync(vin, st);
+  hipFreeAsync(vout, st);
+  hipFreeAsync(rx, st);
+  hipFreeAsync(ry, st);
+  hipFreeAsync(tmp, st);
+  hipFreeAsync(bbox_all, st);
+  hipFreeAsync(bbk, st);
+  hipFreeAsync(axis, st);
+  hipFreeAsync(dlo, st);
   return "";
 }
 

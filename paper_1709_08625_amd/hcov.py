@@ -26,6 +26,16 @@ OBJ_FN = C.CFUNCTYPE(C.c_double, C.POINTER(C.c_double), C.c_int, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
+class Request(C.Structure):
+    _fields_ = [("locs", C.c_void_p), ("n", C.c_int64), ("z", C.c_void_p), ("theta", Theta), ("eps", C.c_double),
+                ("leaf", C.c_int), ("eta", C.c_double), ("dataset", C.c_int)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int), ("loglik", C.c_double), ("logdet", C.c_double), ("quad", C.c_double),
+                ("queue_ms", C.c_double), ("service_ms", C.c_double), ("latency_ms", C.c_double)]
+
+
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("max_rank", C.c_int), ("aca_eps_factor", C.c_double),
                 ("fuse_solve", C.c_int), ("mem_cap_bytes", C.c_size_t), ("alloc", ALLOC_FN),
@@ -80,6 +90,15 @@ def lib():
                                        C.POINTER(C.c_int), dp, dp]
         L.hcov_fit.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, C.c_double, C.c_int, C.c_double, dp, dp,
                                C.POINTER(C.c_int), dp, dp]
+        L.hcov_server_create.argtypes = [C.c_int, C.c_size_t, C.POINTER(Opts), C.POINTER(C.c_void_p)]
+        L.hcov_server_dataset.argtypes = [C.c_void_p, dp, C.c_int64, Theta, C.c_double, C.c_int, C.c_double,
+                                          C.POINTER(C.c_int)]
+        L.hcov_server_release.argtypes = [C.c_void_p, C.c_int]
+        L.hcov_server_submit.argtypes = [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.hcov_server_poll.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Result)]
+        L.hcov_server_wait.argtypes = [C.c_void_p, C.c_uint64, C.POINTER(Result)]
+        L.hcov_server_destroy.argtypes = [C.c_void_p]
+        L.hcov_server_destroy.restype = None
         L.hcov_profile_begin.argtypes = [C.c_void_p, C.c_int]
         L.hcov_profile_end.argtypes = [C.c_void_p, C.POINTER(C.c_int64), dp, dp]
         _lib = L
@@ -89,7 +108,11 @@ def lib():
 EXPORTS = ["hcov_opts_default", "hcov_build", "hcov_set_theta", "hcov_cholesky", "hcov_logdet", "hcov_solve",
            "hcov_forward", "hcov_sample", "hcov_matvec", "hcov_loglik", "hcov_stats", "hcov_estimate_bytes",
            "hcov_perm", "hcov_destroy", "hcov_strerror", "hcov_last_error", "hcov_tree_sizes", "hcov_tree_dump",
-           "hcov_matern_eval", "hcov_profile_begin", "hcov_profile_end", "hcov_nm_minimize", "hcov_fit"]
+           "hcov_matern_eval", "hcov_profile_begin", "hcov_profile_end", "hcov_nm_minimize", "hcov_fit",
+           "hcov_server_create", "hcov_server_dataset", "hcov_server_release", "hcov_server_submit",
+           "hcov_server_poll", "hcov_server_wait", "hcov_server_destroy"]
+
+EAGAIN = -7
 
 STAGE_KINDS = {"gemm": 0, "tsqr_seg": 1, "tsqr_red": 2, "small": 3, "leaf": 4, "trsm": 5}
 
@@ -326,3 +349,77 @@ class HCov:
         blocks = np.empty(nb.value * 4, dtype=np.int64)
         self._chk(lib().hcov_tree_dump(self._ctx, _dp(bbox), blocks.ctypes.data_as(C.POINTER(C.c_int64))))
         return d.value, bbox.reshape(-1, 4), blocks.reshape(-1, 4)
+
+
+class Server:
+    """Request loop of the library (worker threads with one HIP stream each,
+    admission by device-memory estimate, resident data sets)."""
+
+    def __init__(self, slots=4, mem_budget=0, opts=None):
+        o = default_opts(**(opts or {}))
+        h = C.c_void_p()
+        rc = lib().hcov_server_create(int(slots), C.c_size_t(int(mem_budget)), C.byref(o), C.byref(h))
+        if rc:
+            raise HcovError(rc, lib().hcov_strerror(rc).decode())
+        self._h = h
+
+    def _chk(self, rc):
+        if rc:
+            raise HcovError(rc, lib().hcov_strerror(rc).decode())
+
+    def dataset(self, locs, theta, eps=1e-8, leaf=64, eta=2.0):
+        """Registers resident locations; returns the data-set id."""
+        locs = np.ascontiguousarray(locs, dtype=np.float64)
+        i = C.c_int()
+        self._chk(lib().hcov_server_dataset(self._h, _dp(locs), locs.shape[0], _theta(theta), float(eps), int(leaf),
+                                            float(eta), C.byref(i)))
+        return i.value
+
+    def release(self, ds):
+        self._chk(lib().hcov_server_release(self._h, int(ds)))
+
+    def submit(self, z, theta, locs=None, eps=1e-8, leaf=64, eta=2.0, dataset=0):
+        """Queues one evaluation; returns its ticket."""
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        r = Request()
+        keep = [z]
+        if locs is not None:
+            locs = np.ascontiguousarray(locs, dtype=np.float64)
+            keep.append(locs)
+            r.locs = locs.ctypes.data
+        r.n = z.shape[0]
+        r.z = z.ctypes.data
+        r.theta = _theta(theta)
+        r.eps, r.leaf, r.eta, r.dataset = float(eps), int(leaf), float(eta), int(dataset)
+        t = C.c_uint64()
+        self._chk(lib().hcov_server_submit(self._h, C.byref(r), C.byref(t)))
+        return t.value
+
+    @staticmethod
+    def _res(r):
+        return {f: getattr(r, f) for f, _ in Result._fields_}
+
+    def poll(self, ticket):
+        """Result dict when done, None while pending."""
+        r = Result()
+        rc = lib().hcov_server_poll(self._h, C.c_uint64(ticket), C.byref(r))
+        if rc == EAGAIN:
+            return None
+        self._chk(rc)
+        return self._res(r)
+
+    def wait(self, ticket):
+        r = Result()
+        self._chk(lib().hcov_server_wait(self._h, C.c_uint64(ticket), C.byref(r)))
+        return self._res(r)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().hcov_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -60,3 +60,19 @@ def test_argument_validation_on_host():
     with pytest.raises(hcov.HcovError) as e:
         hcov.HCov(locs2, (1.0, 0.1, 0.5, 1e-4))
     assert e.value.code == hcov.EINVAL
+
+
+def test_server_argument_validation_on_host():
+    import ctypes as C
+
+    L = hcov.lib()
+    h = C.c_void_p()
+    assert L.hcov_server_create(0, 0, None, C.byref(h)) == hcov.EINVAL
+    assert L.hcov_server_create(65, 0, None, C.byref(h)) == hcov.EINVAL
+    assert L.hcov_server_create(2, 0, None, None) == hcov.EINVAL
+    t = C.c_uint64()
+    assert L.hcov_server_submit(None, None, C.byref(t)) == hcov.EINVAL
+    r = hcov.Result()
+    assert L.hcov_server_poll(None, 1, C.byref(r)) == hcov.EINVAL
+    assert L.hcov_server_wait(None, 1, C.byref(r)) == hcov.EINVAL
+    assert L.hcov_strerror(hcov.EAGAIN) == b"not completed yet"

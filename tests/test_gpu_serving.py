@@ -1,0 +1,93 @@
+"""Serving (request loop with concurrent slots, memory admission, resident
+data sets): every result is bit-identical to the same evaluation run alone.
+Inputs follow the serving workload: n log-uniform, uniform locations,
+theta uniform in the stated boxes; z is a standard normal vector."""
+import numpy as np
+import pytest
+
+import workloads
+from paper_1709_08625_amd import hcov
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(count, seed, n_lo=800, n_hi=6000):
+    out = []
+    rng = np.random.default_rng(seed)
+    for i in range(count):
+        n = int(np.floor(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        locs, z = workloads.uniform(n, seed=1000 + i)
+        th = (rng.uniform(0.5, 2.0), rng.uniform(0.02, 0.3), rng.uniform(0.3, 2.5), 1e-4)
+        out.append((locs, z, th))
+    return out
+
+
+def _alone(locs, z, th, eps, leaf, eta):
+    H = hcov.HCov(locs, th, eps=eps, leaf=leaf, eta=eta)
+    try:
+        return H.loglik(z)
+    finally:
+        H.close()
+
+
+def test_mix_equals_alone():
+    eps, leaf, eta = 1e-8, 64, 2.0
+    reqs = _requests(10, seed=3)
+    alone = [_alone(l, z, th, eps, leaf, eta) for l, z, th in reqs]
+    S = hcov.Server(slots=4)
+    try:
+        tickets = [S.submit(z, th, locs=l, eps=eps, leaf=leaf, eta=eta) for l, z, th in reqs]
+        res = [S.wait(t) for t in tickets]
+    finally:
+        S.close()
+    for (ll, ld, q), r in zip(alone, res):
+        assert r["status"] == 0
+        assert (r["loglik"], r["logdet"], r["quad"]) == (ll, ld, q)
+        assert r["latency_ms"] >= r["service_ms"] > 0.0
+
+
+def test_small_budget_still_serves_one_at_a_time():
+    eps, leaf, eta = 1e-8, 64, 2.0
+    reqs = _requests(3, seed=5, n_hi=3000)
+    alone = [_alone(l, z, th, eps, leaf, eta) for l, z, th in reqs]
+    S = hcov.Server(slots=3, mem_budget=1)
+    try:
+        tickets = [S.submit(z, th, locs=l, eps=eps, leaf=leaf, eta=eta) for l, z, th in reqs]
+        res = [S.wait(t) for t in tickets]
+        with pytest.raises(hcov.HcovError):
+            S.poll(tickets[0])       # a result is handed out once
+    finally:
+        S.close()
+    for (ll, ld, q), r in zip(alone, res):
+        assert (r["loglik"], r["logdet"], r["quad"]) == (ll, ld, q)
+
+
+def test_resident_dataset_matches_context():
+    eps, leaf, eta = 1e-8, 64, 2.0
+    locs, z = workloads.uniform(4000, seed=11)
+    thetas = [(1.0, 0.1, 0.8, 1e-4), (1.3, 0.07, 1.1, 1e-4), (0.8, 0.15, 0.6, 1e-4)]
+    H = hcov.HCov(locs, thetas[0], eps=eps, leaf=leaf, eta=eta)
+    try:
+        ref = []
+        for th in thetas:
+            H.set_theta(th)
+            ref.append(H.loglik(z))
+    finally:
+        H.close()
+    S = hcov.Server(slots=2)
+    try:
+        ds = S.dataset(locs, thetas[0], eps=eps, leaf=leaf, eta=eta)
+        tickets = [S.submit(z, th, dataset=ds) for th in thetas]
+        other = _requests(2, seed=9, n_hi=2000)
+        t2 = [S.submit(zz, th, locs=l, eps=eps, leaf=leaf, eta=eta) for l, zz, th in other]
+        res = [S.wait(t) for t in tickets]
+        res2 = [S.wait(t) for t in t2]
+        S.release(ds)
+        with pytest.raises(hcov.HcovError):
+            S.submit(z, thetas[0], dataset=ds)
+    finally:
+        S.close()
+    for (ll, ld, q), r in zip(ref, res):
+        assert (r["loglik"], r["logdet"], r["quad"]) == (ll, ld, q)
+    for (l, zz, th), r in zip(other, res2):
+        assert (r["loglik"], r["logdet"], r["quad"]) == _alone(l, zz, th, eps, leaf, eta)
