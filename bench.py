@@ -60,6 +60,70 @@ def cpu_baseline(n_full, theta, budget_s=20.0):
                       f"(extrapolated: the dense matrix at n={n_full} would need {8 * n_full**2 / 1e12:.1f} TB)"}
 
 
+def serving(args, hcov, workloads):
+    """Serving stream: requests of n log-uniform in [1k, 64k], uniform
+    locations, theta uniform in the stated boxes, z = xi (FP64, eps 1e-8,
+    leaf 64, eta 2, nugget 1e-4).  Three runs of the same requests: the plain
+    path one at a time in arrival order (FIFO), the server with every request
+    queued at once (capacity), and the server under Poisson arrivals at 0.8 x
+    the FIFO throughput (latency)."""
+    eps, leaf, eta, nug = 1e-8, 64, 2.0, 1e-4
+    reqs = workloads.serving_stream(count=args.requests, seed=0, rate=1.0)
+    inputs = [workloads.request_inputs(r) for r in reqs]
+    thetas = [(r["sigma2"], r["ell"], r["nu"], nug) for r in reqs]
+    # warm-up (kernel attributes, allocator pools)
+    w = hcov.HCov(inputs[0][0], thetas[0], eps=eps, leaf=leaf, eta=eta)
+    w.loglik(inputs[0][1])
+    w.close()
+    progress("warm-up done")
+
+    def run(slots, arrivals):
+        S = hcov.Server(slots=slots)
+        t0 = time.perf_counter()
+        tickets = []
+        for (locs, z), th, a in zip(inputs, thetas, arrivals):
+            dt = t0 + a - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(S.submit(z, th, locs=locs, eps=eps, leaf=leaf, eta=eta))
+        res = [S.wait(t) for t in tickets]
+        wall = time.perf_counter() - t0
+        S.close()
+        bad = [r["status"] for r in res if r["status"] != 0]
+        assert not bad, bad
+        lat = np.array([r["latency_ms"] for r in res])
+        return wall, lat, res
+
+    zero = [0.0] * len(reqs)
+    t_fifo, lat_fifo, res_fifo = run(1, zero)
+    progress(f"FIFO plain path: {len(reqs) / t_fifo:.2f} evals/s")
+    t_cap, lat_cap, res_cap = run(args.slots, zero)
+    progress(f"server capacity ({args.slots} slots): {len(reqs) / t_cap:.2f} evals/s")
+    rate = 0.8 * len(reqs) / t_fifo
+    gaps = np.random.default_rng(1).exponential(1.0 / rate, size=len(reqs))
+    arr = list(np.cumsum(gaps) - gaps[0])
+    t_open, lat_open, res_open = run(args.slots, arr)
+    progress(f"server open loop at {rate:.2f} req/s done")
+    same = all((a["loglik"], a["logdet"], a["quad"]) == (b["loglik"], b["logdet"], b["quad"]) == (c["loglik"], c["logdet"], c["quad"])
+               for a, b, c in zip(res_fifo, res_cap, res_open))
+    pct = lambda a, q: float(np.percentile(a, q))
+    return {
+        "metric": "serving: loglik evals/sec over a request stream (n log-uniform 1k-64k); p50/p99 latency",
+        "value": len(reqs) / t_cap, "unit": "evals/s", "n_gpus": 1, "steps": len(reqs), "warmup": 1,
+        "ms_per_step": 1e3 * t_cap / len(reqs), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"serving stream of {len(reqs)} requests, n log-uniform [1000, 64000], uniform "
+                               f"[0,1]^2 locations, sigma2 U[0.5,2], ell U[0.02,0.3], nu U[0.3,2.5], nugget {nug}, "
+                               f"eps {eps}, leaf {leaf}, eta {eta}, z = xi", "slots": args.slots},
+        "fifo_plain_path": {"evals_per_s": len(reqs) / t_fifo, "p50_ms": pct(lat_fifo, 50),
+                            "p99_ms": pct(lat_fifo, 99)},
+        "capacity": {"evals_per_s": len(reqs) / t_cap, "p50_ms": pct(lat_cap, 50), "p99_ms": pct(lat_cap, 99)},
+        "open_loop": {"arrival_rate_per_s": rate, "evals_per_s": len(reqs) / t_open, "p50_ms": pct(lat_open, 50),
+                      "p99_ms": pct(lat_open, 99)},
+        "results_identical_across_runs": bool(same),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +132,9 @@ def main():
     ap.add_argument("--n", type=int, default=512000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-kind", default="gemm")
+    ap.add_argument("--workload", default="loglik512k", choices=["loglik512k", "serving"])
+    ap.add_argument("--requests", type=int, default=96)
+    ap.add_argument("--slots", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -80,6 +147,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.workload == "serving":
+        print(json.dumps(serving(args, hcov, workloads)))
+        return
     n = args.n
     theta0 = (1.0, 0.08, 0.8, 1e-4)
     eps, leaf, eta = 1e-7, 128, 2.0

@@ -57,6 +57,9 @@ struct hcov_ctx {
   LaunchCtx L{};
   // kernel profiling (HIP events around every launch of one stage kind)
   int prof_kind = -1;
+  // second lane of the factorisation sweep (see ST_FORK / ST_JOIN)
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   std::vector<Stage> prof_stages;
   // state
@@ -173,17 +176,28 @@ int tree_depth(int64_t n, int leaf) {
 
 int run_stages(hcov_ctx* c, const std::vector<Stage>& st) {
   for (const Stage& s : st) {
+    if (s.kind == ST_FORK) {
+      HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+      HIPCHK(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+      continue;
+    }
+    if (s.kind == ST_JOIN) {
+      HIPCHK(c, hipEventRecord(c->ev_join, c->stream2));
+      HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+      continue;
+    }
+    hipStream_t sm = s.lane ? c->stream2 : c->stream;
     if (s.kind == c->prof_kind) {
       hipEvent_t a, b;
       HIPCHK(c, hipEventCreate(&a));
       HIPCHK(c, hipEventCreate(&b));
-      HIPCHK(c, hipEventRecord(a, c->stream));
-      HIPCHK(c, launch_stage(s, c->L, c->stream));
-      HIPCHK(c, hipEventRecord(b, c->stream));
+      HIPCHK(c, hipEventRecord(a, sm));
+      HIPCHK(c, launch_stage(s, c->L, sm));
+      HIPCHK(c, hipEventRecord(b, sm));
       c->prof_ev.emplace_back(a, b);
       c->prof_stages.push_back(s);
     } else {
-      HIPCHK(c, launch_stage(s, c->L, c->stream));
+      HIPCHK(c, launch_stage(s, c->L, sm));
     }
   }
   return HCOV_OK;
@@ -382,13 +396,21 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   c->eps = eps;
   c->opts = o;
   c->stream = (hipStream_t)hip_stream;
+  if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+    if (c->stream2) (void)hipStreamDestroy(c->stream2);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    delete c;
+    return HCOV_EDEVICE;
+  }
   c->theta = theta;
   c->D = tree_depth(n, leaf);
   static std::once_flag attr_once;
   static hipError_t attr_err = hipSuccess;
   std::call_once(attr_once, [] { attr_err = setup_kernel_attributes(); });
   if (attr_err != hipSuccess) {
-    delete c;
+    hcov_destroy(c);
     return HCOV_EDEVICE;
   }
   auto bail = [&](int code) {
@@ -782,8 +804,12 @@ int hcov_tree_dump(const hcov_ctx* c, double* bbox, int64_t* blocks) {
 
 void hcov_destroy(hcov_ctx* c) {
   if (!c) return;
+  if (c->stream2) (void)hipStreamSynchronize(c->stream2);
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
+  if (c->stream2) (void)hipStreamDestroy(c->stream2);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
   for (void* p : c->allocs) {
     if (c->opts.free)
       c->opts.free(p, c->opts.alloc_user);

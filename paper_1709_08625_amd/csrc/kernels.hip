@@ -33,17 +33,17 @@ namespace hc {
 constexpr int GT = 64, GK = 32;
 constexpr int GR = GK * GT / 256;   // elements of each operand chunk per thread
 
-template <int NX, int NY>
+template <class T, int NX, int NY>
 __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const int* __restrict__ dyn, const GemmJob& J,
                                           const GemmProd* __restrict__ prods, int m, int n, int r0,
-                                          int c0, double (*As)[GT + 1], double (*Bs)[GT + 1]) {
+                                          int c0, T (*As)[GT + 1], T (*Bs)[GT + 1]) {
   const int tid = threadIdx.x;
   const int ty = tid & 15, tx = tid >> 4;   // rows follow the lane index (coalesced C and tb==2 access)
-  double acc[NX][NY];
+  T acc[NX][NY];
 #pragma unroll
   for (int a = 0; a < NX; ++a)
 #pragma unroll
-    for (int b = 0; b < NY; ++b) acc[a][b] = 0.0;
+    for (int b = 0; b < NY; ++b) acc[a][b] = T(0);
 
   for (int pi = J.p0; pi < J.p1; ++pi) {
     const GemmProd Pd = prods[pi];
@@ -65,13 +65,13 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
         for (int y = 0; y < NY; ++y) {
           int gi = r0 + ty + 16 * x, gj = c0 + tx + 16 * y;
           if (gi >= pr0 && gi < pr1 && gj >= pc0 && gj < pc1)
-            acc[x][y] += alpha * A[(gi - pr0) + (size_t)(gj - pc0) * lda];
+            acc[x][y] += T(alpha * A[(gi - pr0) + (size_t)(gj - pc0) * lda]);
         }
       continue;
     }
     // element e of a chunk: A chunk is GT x GK, B chunk GK x GT; the index
     // split follows the operand's storage order so that lanes coalesce
-    double ra[GR], rb[GR];
+    T ra[GR], rb[GR];
     auto fetch = [&](int k0) {
 #pragma unroll
       for (int r = 0; r < GR; ++r) {
@@ -84,7 +84,7 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
           int li = gi - pr0;
           v = Pd.ta == 0 ? A[li + (size_t)gk * lda] : A[gk + (size_t)li * lda];
         }
-        ra[r] = alpha * v;
+        ra[r] = T(alpha * v);
       }
 #pragma unroll
       for (int r = 0; r < GR; ++r) {
@@ -97,7 +97,7 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
           int lj = gj - pc0;
           v = Pd.tb == 0 ? B[gk + (size_t)lj * ldb] : B[lj + (size_t)gk * ldb];
         }
-        rb[r] = v;
+        rb[r] = T(v);
       }
     };
     fetch(0);
@@ -117,7 +117,7 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
       const int kl = min(GK, k - k0);
 #pragma unroll 8
       for (int kk = 0; kk < kl; ++kk) {
-        double av[NX], bv[NY];
+        T av[NX], bv[NY];
 #pragma unroll
         for (int q = 0; q < NX; ++q) av[q] = As[kk][ty + 16 * q];
 #pragma unroll
@@ -141,7 +141,7 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
       int gj = c0 + tx + 16 * y;
       if (gj >= n) continue;
       size_t o = gi + (size_t)gj * ldc;
-      C[o] = J.zero ? acc[x][y] : C[o] + acc[x][y];
+      C[o] = J.zero ? double(acc[x][y]) : C[o] + double(acc[x][y]);
     }
   }
 }
@@ -159,16 +159,33 @@ __global__ __launch_bounds__(256) void k_gemm(const Bufs* __restrict__ bufs, con
   __shared__ double Bs[GK][GT + 1];
   const int er = min(GT, m - r0), ec = min(GT, n - c0);
   const int nx = er <= 16 ? 1 : (er <= 32 ? 2 : 4), ny = ec <= 16 ? 1 : (ec <= 32 ? 2 : 4);
+  if (J.fp32) {
+    // mixed precision: FP32 tiles in the same LDS storage, FP32 accumulation
+    float(*Af)[GT + 1] = reinterpret_cast<float(*)[GT + 1]>(&As[0][0]);
+    float(*Bf)[GT + 1] = reinterpret_cast<float(*)[GT + 1]>(&Bs[0][0]);
+    switch (nx * 8 + ny) {
+      case 9: gemm_tile<float, 1, 1>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+      case 10: gemm_tile<float, 1, 2>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+      case 12: gemm_tile<float, 1, 4>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+      case 17: gemm_tile<float, 2, 1>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+      case 18: gemm_tile<float, 2, 2>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+      case 20: gemm_tile<float, 2, 4>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+      case 33: gemm_tile<float, 4, 1>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+      case 34: gemm_tile<float, 4, 2>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+      default: gemm_tile<float, 4, 4>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+    }
+    return;
+  }
   switch (nx * 8 + ny) {
-    case 9: gemm_tile<1, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 10: gemm_tile<1, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 12: gemm_tile<1, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 17: gemm_tile<2, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 18: gemm_tile<2, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 20: gemm_tile<2, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 33: gemm_tile<4, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 34: gemm_tile<4, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    default: gemm_tile<4, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 9: gemm_tile<double, 1, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 10: gemm_tile<double, 1, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 12: gemm_tile<double, 1, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 17: gemm_tile<double, 2, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 18: gemm_tile<double, 2, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 20: gemm_tile<double, 2, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 33: gemm_tile<double, 4, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 34: gemm_tile<double, 4, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    default: gemm_tile<double, 4, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
   }
 }
 
@@ -582,6 +599,48 @@ __device__ int qrcp_lds(double* A, int n, double tau, double* cn, double* cn0, i
   return k;
 }
 
+// Householder QR of the n x n matrix M in LDS (ld SM) that keeps the
+// reflectors: on exit R is in the upper triangle, v_j below the diagonal of
+// column j with its leading entry in vtop[j], and H_j = I - beta[j] v_j v_j^T,
+// so that M = H_0 H_1 ... H_{n-1} R.
+__device__ void house_qr_keep(double* M, int n, double* vtop, double* beta, double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int j = 0; j < n; ++j) {
+    if (wave == 0) {
+      double sq = 0.0;
+      for (int i = j + lane; i < n; i += 64) sq += M[i + j * SM] * M[i + j * SM];
+      for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+      if (lane == 0) {
+        const double nrm = sqrt(sq);
+        const double a = M[j + j * SM];
+        const double alpha = (a >= 0.0) ? -nrm : nrm;
+        const double vtv = 2.0 * nrm * (nrm + fabs(a));
+        red[0] = alpha;
+        red[1] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+        M[j + j * SM] = a - alpha;
+      }
+    }
+    __syncthreads();
+    const double b = red[1];
+    if (b != 0.0) {
+      for (int l = j + 1 + wave; l < n; l += 4) {
+        double sdot = 0.0;
+        for (int i = j + lane; i < n; i += 64) sdot += M[i + j * SM] * M[i + l * SM];
+        for (int o = 32; o > 0; o >>= 1) sdot += __shfl_xor(sdot, o);
+        sdot *= b;
+        for (int i = j + lane; i < n; i += 64) M[i + l * SM] -= sdot * M[i + j * SM];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      vtop[j] = M[j + j * SM];
+      beta[j] = b;
+      M[j + j * SM] = red[0];
+    }
+    __syncthreads();
+  }
+}
+
 // Small dense problems built from upper-triangular R factors.
 //   SK_RECOMP   SVD of A = R1 R2^T = X S Y^T (one-sided Jacobi on A):
 //               CU = R2^T Y_k, CV = R1^T X_k S_k^{-1}, k = #{s > eps s_1}
@@ -601,7 +660,8 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
   double* R2 = R1 + SM * (SM + 1) / 2;       // packed upper
   double* sv = R2 + SM * (SM + 1) / 2;       // SM
   double* red = sv + SM;                     // 8
-  int* ord = (int*)(red + 8);                // SM
+  double* beta = red + 8;                    // 2 SM: reflector factors, leading entries
+  int* ord = (int*)(beta + 2 * SM);          // SM
   const int tid = threadIdx.x;
   const double eps = J.eps == -1.0 ? eps_run : (J.eps == -2.0 ? tau_run : J.eps);
   if (n <= 0) {
@@ -659,6 +719,27 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     }
   }
   __syncthreads();
+  // SK_SKETCH_F: with M^T = Q2 R2 (reflectors kept in R1's packed storage,
+  // which is free now), M = R2^T Q2^T, and one-sided Jacobi on B = R2^T
+  // (B V = U S) gives the right singular vectors of M as Q2 V; B converges
+  // in about half the sweeps M itself needs.
+  double* vtop = sv;                    // reused after the reflectors are saved
+  if (J.kind == SK_SKETCH_F) {
+    for (int e = tid; e < n * n; e += 256) {
+      int i = e % n, j = e / n;
+      V[i + j * SM] = A[j + i * SM];
+    }
+    __syncthreads();
+    house_qr_keep(V, n, vtop, beta, red);
+    // reflectors (strictly lower part) to packed storage, B = R2^T into A
+    for (int e = tid; e < n * n; e += 256) {
+      int i = e % n, j = e / n;
+      if (i > j) R1[j * n - j * (j + 1) / 2 + (i - j - 1)] = V[i + j * SM];
+      A[i + j * SM] = (i >= j) ? V[j + i * SM] : 0.0;
+    }
+    for (int j = tid; j < n; j += 256) beta[SM + j] = vtop[j];
+    __syncthreads();
+  }
   {
     const double f2 = fro2_lds(A, n, red);
     const double dt = 1e-3 * eps;
@@ -697,28 +778,56 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
       C2[i + (size_t)c * rmax] = cv / (s * s);
     }
   } else {
-    // C = R2^{-1} Z_k, Z = V[:, ord]: back substitution, one thread per column,
-    // the column kept in A's (now free) storage
+    // Z_k = Q2 V[:, ord[0..k)] into A (reflectors applied last to first),
+    // then C = R2^{-1} Z_k by back substitution, one thread per column, in V
     __syncthreads();
+    for (int e = tid; e < n * kk; e += 256) {
+      int i = e % n, c = e / n;
+      A[i + c * SM] = V[i + ord[c] * SM];
+    }
+    __syncthreads();
+    for (int j = n - 1; j >= 0; --j) {
+      const double b = beta[j];
+      if (b != 0.0) {
+        // v = (vtop_j, v_{j+1..n-1}) on rows j..n-1; column c of Z by one thread
+        const double* vj = R1 + j * n - j * (j + 1) / 2;
+        const double v0 = beta[SM + j];
+        for (int c = tid; c < kk; c += 256) {
+          double d = v0 * A[j + c * SM];
+          for (int i = j + 1; i < n; ++i) d += vj[i - j - 1] * A[i + c * SM];
+          d *= b;
+          A[j + c * SM] -= d * v0;
+          for (int i = j + 1; i < n; ++i) A[i + c * SM] -= d * vj[i - j - 1];
+        }
+      }
+      __syncthreads();
+    }
     for (int c = tid; c < kk; c += 256) {
-      int oc = ord[c];
       for (int i = n - 1; i >= 0; --i) {
-        double acc = V[i + oc * SM];
-        for (int l = i + 1; l < n; ++l) acc -= R2[upk(i, l)] * A[l + c * SM];
+        double acc = A[i + c * SM];
+        for (int l = i + 1; l < n; ++l) acc -= R2[upk(i, l)] * V[l + c * SM];
         double d = R2[upk(i, i)];
-        A[i + c * SM] = (d != 0.0) ? acc / d : 0.0;
+        V[i + c * SM] = (d != 0.0) ? acc / d : 0.0;
       }
     }
     __syncthreads();
     for (int e = tid; e < n * kk; e += 256) {
       int i = e % n, c = e / n;
-      C1[i + (size_t)c * rmax] = A[i + c * SM];
+      C1[i + (size_t)c * rmax] = V[i + c * SM];
     }
   }
   if (tid == 0) dyn[J.out_rank_slot] = kk;
 }
 
 // ------------------------------------------------------------------ leaf
+// value of v in lane `lane` (uniform) of the wave
+__device__ __forceinline__ double wave_bcast(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // Diagonal leaf factorisation (potrf, lower) of an updated tile of order
 // p <= 128.  Each thread owns an 8 x 8 block of the tile in registers (rows
 // ty + 16a with ty the lane index mod 16, so that loads coalesce; columns
@@ -744,8 +853,12 @@ __global__ __launch_bounds__(256) void k_leaf(const Bufs* __restrict__ bufs, con
       int i = ty + 16 * a, j = tx + 16 * b;
       acc[a][b] = (i < p && j < p) ? Dp[i + (size_t)j * ldd] : 0.0;
     }
+  __shared__ int s_bad;
+  if (tid == 0) s_bad = -1;
   int bad = -1;
-#pragma unroll
+  // register arrays are only indexed by compile-time constants (predicated
+  // copies), so that nothing is demoted to indexed register access
+#pragma unroll 1
   for (int bb = 0; bb < LF / LPW; ++bb) {
     const int jb = bb * LPW;
     if (jb >= p || bad >= 0) break;
@@ -753,45 +866,87 @@ __global__ __launch_bounds__(256) void k_leaf(const Bufs* __restrict__ bufs, con
     // panel columns jb..jb+w-1 (owned by the threads' column group bb) to LDS;
     // rows above the panel are zero
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      int i = ty + 16 * a;
-      Pn[i * LPLD + tx] = (i >= jb && i < p) ? acc[a][bb] : 0.0;
+    for (int b = 0; b < LF / LPW; ++b) {
+      if (b == bb) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          int i = ty + 16 * a;
+          Pn[i * LPLD + tx] = (i >= jb && i < p) ? acc[a][b] : 0.0;
+        }
+      }
     }
     __syncthreads();
-    // factorise the panel: thread r < p - jb owns row jb + r
-    const int i = jb + tid;
-    for (int c = 0; c < w; ++c) {
-      const double d = Pn[(jb + c) * LPLD + c];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = jb + c;
-        break;
+    // the first wave factorises the panel in registers: lane l holds rows
+    // jb + l and jb + 64 + l; the pivot row jb + c is lane c, and the entries
+    // of column c needed by every lane are read with readlane
+    if (tid < 64) {
+      const int lane = tid;
+      const int ra = jb + lane, rb = jb + 64 + lane;
+      double x0[LPW], x1[LPW];
+#pragma unroll
+      for (int c = 0; c < LPW; ++c) {
+        x0[c] = ra < p ? Pn[ra * LPLD + c] : 0.0;
+        x1[c] = rb < p ? Pn[rb * LPLD + c] : 0.0;
       }
-      const double ljj = sqrt(d);
-      __syncthreads();   // every thread has read d
-      if (i < p && i >= jb + c) Pn[i * LPLD + c] = (i == jb + c) ? ljj : Pn[i * LPLD + c] / ljj;
-      if (tid == 0) dg[jb + c] = ljj;
-      __syncthreads();
-      if (i < p && i > jb + c) {
-        const double lic = Pn[i * LPLD + c];
-        for (int c2 = c + 1; c2 < w && jb + c2 <= i; ++c2) Pn[i * LPLD + c2] -= lic * Pn[(jb + c2) * LPLD + c];
+      int wbad = -1;
+#pragma unroll
+      for (int c = 0; c < LPW; ++c) {
+        if (c < w && wbad < 0) {
+          const double d = wave_bcast(x0[c], c);
+          if (!(d > 0.0) || !isfinite(d)) {
+            wbad = jb + c;
+          } else {
+            const double ljj = sqrt(d), inv = 1.0 / ljj;
+            if (lane == c)
+              x0[c] = ljj;
+            else if (lane > c)
+              x0[c] *= inv;
+            x1[c] *= inv;
+            if (lane == 0) dg[jb + c] = ljj;
+#pragma unroll
+            for (int c2 = c + 1; c2 < LPW; ++c2) {
+              if (c2 < w) {
+                const double l = wave_bcast(x0[c], c2);
+                if (lane >= c2) x0[c2] = fma(-x0[c], l, x0[c2]);
+                x1[c2] = fma(-x1[c], l, x1[c2]);
+              }
+            }
+          }
+        }
       }
-      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < LPW; ++c) {
+        if (ra < p) Pn[ra * LPLD + c] = x0[c];
+        if (rb < p) Pn[rb * LPLD + c] = x1[c];
+      }
+      if (lane == 0) s_bad = wbad;
     }
+    __syncthreads();
+    bad = s_bad;
     if (bad >= 0) break;
     // factorised panel back to the owners; trailing update of later columns
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-      int r = ty + 16 * a;
-      acc[a][bb] = (r >= jb + tx && r < p) ? Pn[r * LPLD + tx] : 0.0;
+    for (int b = 0; b < LF / LPW; ++b) {
+      if (b == bb) {
+#pragma unroll
+        for (int a = 0; a < 8; ++a) {
+          int r = ty + 16 * a;
+          acc[a][b] = (r >= jb + tx && r < p) ? Pn[r * LPLD + tx] : 0.0;
+        }
+      }
     }
+#pragma unroll 2
+    for (int c = 0; c < w; ++c) {
+      double av[8];
 #pragma unroll
-    for (int b = bb + 1; b < LF / LPW; ++b) {
-      if (b * 16 >= p) break;
-#pragma unroll 4
-      for (int c = 0; c < w; ++c) {
-        double lj = Pn[(tx + 16 * b) * LPLD + c];
+      for (int a = 0; a < 8; ++a) av[a] = Pn[(ty + 16 * a) * LPLD + c];
 #pragma unroll
-        for (int a = 0; a < 8; ++a) acc[a][b] = fma(-Pn[(ty + 16 * a) * LPLD + c], lj, acc[a][b]);
+      for (int b = 1; b < LF / LPW; ++b) {
+        if (b > bb && b * 16 < p) {
+          const double lj = Pn[(tx + 16 * b) * LPLD + c];
+#pragma unroll
+          for (int a = 0; a < 8; ++a) acc[a][b] = fma(-av[a], lj, acc[a][b]);
+        }
       }
     }
     __syncthreads();   // the panel buffer is rewritten by the next panel
@@ -1230,7 +1385,7 @@ __global__ void k_fill_value(double* __restrict__ out, int64_t n, double v) {
 }
 
 constexpr size_t LDS_QR = (size_t(QR_LDS) + 8) * 8;
-constexpr size_t LDS_SMALL = (size_t(2) * SM * SM + size_t(SM) * (SM + 1) + SM + 8) * 8 + SM * 4;
+constexpr size_t LDS_SMALL = (size_t(2) * SM * SM + size_t(SM) * (SM + 1) + SM + 8 + 2 * SM) * 8 + SM * 4;
 constexpr size_t LDS_LEAF = size_t(LF * LPLD + LF) * 8;
 constexpr size_t LDS_TRSM = (size_t(LF) * (LF + 1) / 2 + size_t(LF) * 64) * 8;
 

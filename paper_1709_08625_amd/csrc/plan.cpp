@@ -131,13 +131,18 @@ class Builder {
   }
 
   // ---------------------------------------------------------------- GEMM
-  int32_t gemm_job(Ref C, Dim m, Dim n, int zero) {
+  bool fp32_for(const Ref& C) const { return P.mixed && C.buf != B_DENSE && C.buf != B_RHS; }
+  // fp32 < 0: from the output buffer (partial sums take their job's choice)
+  int32_t gemm_job(Ref C, Dim m, Dim n, int zero, int fp32 = -1) {
     GemmJob j{};
     j.C = C;
     j.m = m;
     j.n = n;
     j.zero = zero;
     j.p0 = j.p1 = 0;
+    // mixed precision: every GEMM except those producing dense leaves or the
+    // right-hand side of the fused solve accumulates in FP32
+    j.fp32 = fp32 >= 0 ? fp32 : (fp32_for(C) ? 1 : 0);
     P.gjobs.push_back(j);
     pending_prods.emplace_back();
     return int32_t(P.gjobs.size() - 1);
@@ -414,7 +419,7 @@ class Builder {
       Deferred fin{d.C, d.m, d.n, d.zero, {}};
       for (auto& g : groups) {
         int64_t pb = scr_alloc(int64_t(mcap) * ncap);
-        int32_t j = gemm_job(Ref{B_SCR, mcap, pb}, d.m, d.n, 1);
+        int32_t j = gemm_job(Ref{B_SCR, mcap, pb}, d.m, d.n, 1, fp32_for(d.C) ? 1 : 0);
         for (auto& p : g) add_prod(j, p.A, p.ta, p.B, p.tb, p.k, p.i0, p.j0, p.mi, p.nj, p.alpha);
         dprod(fin, Ref{B_SCR, mcap, pb}, 0, Ref{B_SCR, mcap, pb}, 2, dim_static(1), 0, 0, d.m, d.n, 1.0);
       }
@@ -616,6 +621,55 @@ class Builder {
   }
 
   // ---------------------------------------------------------------- the sweep
+  // triangular-solve jobs X <- L_jj^{-1} X (in 64-column chunks)
+  void add_trsm(int64_t j, Ref X, int layout, Dim nc) {
+    const BlockInfo& Dg = P.blocks[P.diag_block[j]];
+    const int pj = int(Dg.r1 - Dg.r0);
+    Ref Lr{B_DENSE, pj, Dg.off_d};
+    for (int c0 = 0; c0 < nc.maxv; c0 += 64)
+      P.trsms.push_back(TrsmJob{Lr, pj, layout, X, nc, c0, std::min(64, nc.maxv - c0)});
+  }
+  template <class T>
+  static std::vector<int32_t> lrs_ids(const std::vector<T>& lrs) {
+    std::vector<int32_t> v;
+    for (auto& t : lrs) v.push_back(t.b);
+    return v;
+  }
+  std::vector<std::vector<int32_t>> active;   // LR blocks whose column cluster contains leaf j
+  // Once the dense targets of step j are updated, a second lane (stream)
+  // factorises the diagonal leaf and applies L_jj^{-1} to the dense targets,
+  // the panels of the low-rank blocks that started before j and the fused
+  // right-hand side, while the first lane recompresses the new low-rank
+  // targets: the two sets of work touch disjoint data.
+  void fork_leaf(int64_t j, const std::vector<std::pair<int32_t, std::vector<Term>>>& dns,
+                 const std::vector<int32_t>& fresh, bool fuse_rhs, std::vector<Stage>& st) {
+    st.push_back(Stage{ST_FORK, 0, 0});
+    const BlockInfo& B = P.blocks[P.diag_block[j]];
+    LeafJob J{};
+    J.D = Ref{B_DENSE, int32_t(B.r1 - B.r0), B.off_d};
+    J.p = int32_t(B.r1 - B.r0);
+    J.leaf = int32_t(j);
+    J.row0 = B.r0;
+    int32_t l0 = int32_t(P.leafs.size());
+    P.leafs.push_back(J);
+    st.push_back(Stage{ST_LEAF, l0, l0 + 1, 1});
+    const int64_t cj0 = lo(P.D, j);
+    int32_t t0 = int32_t(P.trsms.size());
+    for (auto& dt : dns) {
+      const BlockInfo& T = P.blocks[dt.first];
+      if (T.a == T.c) continue;
+      add_trsm(j, Ref{B_DENSE, int32_t(T.r1 - T.r0), T.off_d}, 1, dim_static(int(T.r1 - T.r0)));
+    }
+    for (int32_t b : active[j]) {
+      if (std::find(fresh.begin(), fresh.end(), b) != fresh.end()) continue;
+      const BlockInfo& T = P.blocks[b];
+      add_trsm(j, Ref{B_V, int32_t(T.c1 - T.c0), T.off_v + (cj0 - T.c0)}, 0, rank_dim(b));
+    }
+    if (fuse_rhs) add_trsm(j, Ref{B_RHS, int32_t(P.rhs_ld), cj0}, 0, dim_static(1));
+    int32_t t1 = int32_t(P.trsms.size());
+    if (t1 > t0) st.push_back(Stage{ST_TRSM, t0, t1, 1});
+  }
+
   void build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps);
   void build_recompress();
   void build_solves();
@@ -631,7 +685,7 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
     by_start[int64_t(B.c) << (D - B.level)].push_back(b);
   }
   // LR blocks whose column cluster contains leaf j are "active" at j
-  std::vector<std::vector<int32_t>> active(m);
+  active.assign(m, {});
   std::unordered_map<uint64_t, std::vector<int32_t>> by_col;
   for (int32_t b = 0; b < int32_t(P.blocks.size()); ++b) {
     const BlockInfo& B = P.blocks[b];
@@ -682,7 +736,10 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         dprod(listA[d], T.U.ref, 0, T.V.ref, 1, T.U.cols, int(T.r0 - B.r0), int(T.p0 - B.c0),
               dim_static(int(T.r1 - T.r0)), dim_static(int(T.p1 - T.p0)), -1.0);
     }
-    if (lrs.empty()) emit(listA, st);
+    if (lrs.empty()) {
+      emit(listA, st);
+      fork_leaf(j, dns, lrs_ids(lrs), fuse_rhs, st);
+    }
 
     // ---- randomised recompression of low-rank targets
     if (!lrs.empty()) {
@@ -730,6 +787,7 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         }
       }
       emit(listA, st);
+      fork_leaf(j, dns, lrs_ids(lrs), fuse_rhs, st);
       // Y = U_A P1_A - sum U_t P1_t
       for (size_t t = 0; t < lrs.size(); ++t) {
         const BlockInfo& B = P.blocks[sk[t].b];
@@ -840,39 +898,15 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
       emit(listA, st);
     }
 
-    // ---- diagonal leaf: potrf (its update was applied by the GEMM stage)
-    {
-      const int32_t db = P.diag_block[j];
-      const BlockInfo& B = P.blocks[db];
-      LeafJob J{};
-      J.D = Ref{B_DENSE, int32_t(B.r1 - B.r0), B.off_d};
-      J.p = int32_t(B.r1 - B.r0);
-      J.leaf = int32_t(j);
-      J.row0 = B.r0;
-      int32_t l0 = int32_t(P.leafs.size());
-      P.leafs.push_back(J);
-      st.push_back(Stage{ST_LEAF, l0, l0 + 1});
-    }
-
-    // ---- triangular solves with L_jj
+    // ---- second lane joins; then the leaf-j rows of the low-rank targets
+    // that started at j (their V was produced by the recompression above)
+    st.push_back(Stage{ST_JOIN, 0, 0});
     {
       int32_t t0 = int32_t(P.trsms.size());
-      const BlockInfo& Dg = P.blocks[P.diag_block[j]];
-      Ref Lr{B_DENSE, pj, Dg.off_d};
-      auto add = [&](Ref X, int layout, Dim nc) {
-        for (int c0 = 0; c0 < nc.maxv; c0 += 64)
-          P.trsms.push_back(TrsmJob{Lr, pj, layout, X, nc, c0, std::min(64, nc.maxv - c0)});
-      };
-      for (auto& dt : dns) {
-        const BlockInfo& B = P.blocks[dt.first];
-        if (B.a == B.c) continue;
-        add(Ref{B_DENSE, int32_t(B.r1 - B.r0), B.off_d}, 1, dim_static(int(B.r1 - B.r0)));
+      for (auto& t : lrs) {
+        const BlockInfo& B = P.blocks[t.b];
+        add_trsm(j, Ref{B_V, int32_t(B.c1 - B.c0), B.off_v + (cj0 - B.c0)}, 0, rank_dim(t.b));
       }
-      for (int32_t b : active[j]) {
-        const BlockInfo& B = P.blocks[b];
-        add(Ref{B_V, int32_t(B.c1 - B.c0), B.off_v + (cj0 - B.c0)}, 0, rank_dim(b));
-      }
-      if (fuse_rhs) add(Ref{B_RHS, int32_t(P.rhs_ld), cj0}, 0, dim_static(1));
       int32_t t1 = int32_t(P.trsms.size());
       if (t1 > t0) st.push_back(Stage{ST_TRSM, t0, t1});
     }
@@ -1127,8 +1161,8 @@ void Builder::build_matvec() {
 
 std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, int64_t nb,
                        int kcap, int oversample, bool mixed) {
-  (void)mixed;
   P = Plan();
+  P.mixed = mixed;
   P.n = n;
   P.D = D;
   P.leaf = leaf;
@@ -1218,7 +1252,8 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
   Bd.build_matvec();
   if (Bd.dyn_max > P.n_dyn) P.n_dyn = Bd.dyn_max;
   int64_t launches = 0;
-  for (auto& s : P.steps) launches += int64_t(s.size());
+  for (auto& s : P.steps)
+    for (auto& x : s) launches += (x.kind != ST_FORK && x.kind != ST_JOIN) ? 1 : 0;
   P.n_launch_fact = launches;
   return "";
 }

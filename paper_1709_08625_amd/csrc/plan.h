@@ -61,6 +61,7 @@ struct GemmJob {
   Dim m, n;          // extent of C written by this job
   int32_t zero;      // 1: C := sum (C is overwritten on its m x n extent)
   int32_t p0, p1;    // products [p0, p1)
+  int32_t fp32;      // 1: products accumulated in FP32 (mixed precision)
 };
 
 // Tile of a GEMM launch (capacity-based grid, dynamic tiles exit early).
@@ -130,10 +131,14 @@ struct TrsmJob {
 };
 
 // ---------------------------------------------------------------- stages
-enum StageKind : int32_t { ST_GEMM = 0, ST_TSQR_SEG, ST_TSQR_RED, ST_SMALL, ST_LEAF, ST_TRSM, ST_COPY_RANK };
+// ST_FORK: the second lane (stream) waits for the work issued so far on the
+// first; ST_JOIN: the first lane waits for the work issued on the second.
+enum StageKind : int32_t { ST_GEMM = 0, ST_TSQR_SEG, ST_TSQR_RED, ST_SMALL, ST_LEAF, ST_TRSM, ST_COPY_RANK,
+                           ST_FORK, ST_JOIN };
 struct Stage {
   int32_t kind;
   int32_t begin, end;   // item range in the kind's array (tiles for GEMM)
+  int32_t lane = 0;     // 0: the context's stream, 1: its second stream
 };
 
 // ---------------------------------------------------------------- tree data
@@ -149,6 +154,7 @@ struct BlockInfo {
 struct Plan {
   // structure
   int64_t n = 0;
+  bool mixed = false;   // low-rank GEMM work in FP32 (dense leaves, potrf, solves FP64)
   int D = 0, leaf = 0, kcap = 64, rcap = 74, oversample = 10, rmax = 80;
   std::vector<std::vector<int64_t>> lo;   // lo[l][i] node start (size 2^l + 1 incl. end)
   std::vector<BlockInfo> blocks;

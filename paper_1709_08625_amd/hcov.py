@@ -211,6 +211,8 @@ class HCov:
         self.n = locs.shape[0]
         if opts is None:
             opts = default_opts()
+        elif isinstance(opts, dict):
+            opts = default_opts(**opts)
         self._cb = None
         if torch_alloc:
             self._cb = torch_allocator()
