@@ -221,12 +221,13 @@ int hcov_fit(hcov_ctx* ctx, const double* z, int where, const double* theta0, co
 
 /* Kernel timing: between hcov_profile_begin(ctx, kind) and
  * hcov_profile_end, every launch of the given stage kind (0 grouped GEMM,
- * 1 TSQR segment, 2 TSQR reduce, 3 small SVD, 4 dense leaf update/potrf,
- * 5 triangular solve) is bracketed by HIP events on the context's stream.
- * hcov_profile_end synchronises and returns the launch count, the summed
- * event time (ms) and the algorithmic FP64 flops of those launches (GEMM:
- * 2 m n k per product; leaf: 2 m n k per term + p^3/3; trsm: p^2 per column;
- * 0 for the other kinds). */
+ * 1 TSQR segment, 2 TSQR reduce, 3 small SVD / pivoted QR, 4 diagonal leaf
+ * potrf, 5 triangular solve, 9 multiplication by a stored leaf inverse) is
+ * bracketed by HIP events on the stream it runs on.  hcov_profile_end
+ * synchronises and returns the launch count, the summed event time (ms) and
+ * the algorithmic FP64 flops of those launches (GEMM: 2 m n k per product;
+ * potrf: p^3/3; solve and multiplication: p^2 per column; 0 for the other
+ * kinds).  Other values of kind are EINVAL. */
 int hcov_profile_begin(hcov_ctx* ctx, int stage_kind);
 int hcov_profile_end(hcov_ctx* ctx, int64_t* launches, double* total_ms, double* flops);
 

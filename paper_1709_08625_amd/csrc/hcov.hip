@@ -229,7 +229,7 @@ double stage_flops(const Plan& P, const std::vector<int>& dyn, const Stage& s) {
     }
   } else if (s.kind == ST_LEAF) {
     for (int t = s.begin; t < s.end; ++t) f += double(P.leafs[t].p) * P.leafs[t].p * P.leafs[t].p / 3.0;
-  } else if (s.kind == ST_TRSM) {
+  } else if (s.kind == ST_TRSM || s.kind == ST_TRMM) {
     for (int t = s.begin; t < s.end; ++t) {
       const TrsmJob& J = P.trsms[t];
       int nc = dyn_value(dyn, J.ncols);
@@ -480,7 +480,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   Plan& P = c->plan;
   // memory estimate check
   size_t need = size_t(P.dense_elems + P.u_elems + P.v_elems + P.scr_elems + P.pers_elems + P.omega_rows * P.rcap +
-                       2 * P.rhs_ld) * 8;
+                       2 * P.rhs_ld + P.linv_elems) * 8;
   if (o.mem_cap_bytes && need > o.mem_cap_bytes) {
     c->err = "estimate " + std::to_string(need) + " bytes exceeds the memory cap";
     return bail(HCOV_ENOMEM);
@@ -492,6 +492,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   c->d_buf[B_OMEGA] = (double*)dev_alloc(c, P.omega_rows * P.rcap * 8);
   c->d_buf[B_RHS] = (double*)dev_alloc(c, 2 * P.rhs_ld * 8);
   c->d_buf[B_PERS] = (double*)dev_alloc(c, P.pers_elems * 8);
+  c->d_buf[B_LINV] = (double*)dev_alloc(c, P.linv_elems * 8);
   c->d_dyn = (int*)dev_alloc(c, (P.n_dyn + 1) * 4);
   c->d_status = (int*)dev_alloc(c, 16);
   int64_t m = int64_t(1) << c->D;
@@ -820,7 +821,9 @@ void hcov_destroy(hcov_ctx* c) {
 }
 
 int hcov_profile_begin(hcov_ctx* c, int stage_kind) {
-  if (!c || stage_kind < 0 || stage_kind > ST_TRSM) return HCOV_EINVAL;
+  if (!c || stage_kind < 0 || stage_kind > ST_TRMM || stage_kind == ST_COPY_RANK || stage_kind == ST_FORK ||
+      stage_kind == ST_JOIN)
+    return HCOV_EINVAL;
   c->prof_kind = stage_kind;
   c->prof_ev.clear();
   c->prof_stages.clear();

@@ -966,9 +966,12 @@ __global__ __launch_bounds__(256) void k_leaf(const Bufs* __restrict__ bufs, con
       int i = ty + 16 * a, j = tx + 16 * b;
       if (i < p && j < p) Dp[i + (size_t)j * ldd] = (i >= j) ? acc[a][b] : 0.0;
     }
+  // log of the diagonal in parallel, summed in index order by one thread
+  for (int j = tid; j < p; j += 256) Pn[j] = log(dg[j]);
+  __syncthreads();
   if (tid == 0) {
     double s = 0.0;
-    for (int j = 0; j < p; ++j) s += log(dg[j]);
+    for (int j = 0; j < p; ++j) s += Pn[j];
     logdet[J.leaf] = s;
   }
 }
@@ -1025,8 +1028,11 @@ __global__ __launch_bounds__(256) void k_trsm(const Bufs* __restrict__ bufs, con
         i = e % p;
         c = e / p;
       }
-      r[u] = (e < p * 64 && c < cw) ? (J.layout == 1 ? X[(J.c0 + c) + (size_t)i * ldx] : X[i + (size_t)(J.c0 + c) * ldx])
-                                    : 0.0;
+      if (J.layout == 3)
+        r[u] = (e < p * 64 && c < cw && i == J.c0 + c) ? 1.0 : 0.0;   // columns of the identity
+      else
+        r[u] = (e < p * 64 && c < cw) ? (J.layout == 1 ? X[(J.c0 + c) + (size_t)i * ldx] : X[i + (size_t)(J.c0 + c) * ldx])
+                                      : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -1050,17 +1056,28 @@ __global__ __launch_bounds__(256) void k_trsm(const Bufs* __restrict__ bufs, con
     for (int b0 = 0; b0 < p; b0 += TB) {
       const int b1 = min(b0 + TB, p);
       if (tid < cw) {
-        for (int i = b0; i < b1; ++i) {
-          const double* Li = Lp + i * (i + 1) / 2;
-          double s0 = Xs[i * 64 + tid], s1 = 0.0;
-          int j = b0;
-          for (; j + 1 < i; j += 2) {
-            s0 -= Li[j] * Xs[j * 64 + tid];
-            s1 -= Li[j + 1] * Xs[(j + 1) * 64 + tid];
+        // the block's 16 unknowns of this column stay in registers
+        double xr[TB];
+#pragma unroll
+        for (int u = 0; u < TB; ++u) xr[u] = (b0 + u < b1) ? Xs[(b0 + u) * 64 + tid] : 0.0;
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          if (b0 + u < b1) {
+            const double* Li = Lp + (b0 + u) * (b0 + u + 1) / 2 + b0;
+            double s0 = xr[u], s1 = 0.0;
+#pragma unroll
+            for (int v = 0; v < u; ++v) {
+              if (v & 1)
+                s1 = fma(-Li[v], xr[v], s1);
+              else
+                s0 = fma(-Li[v], xr[v], s0);
+            }
+            xr[u] = (s0 + s1) * rdiag[b0 + u];
           }
-          if (j < i) s0 -= Li[j] * Xs[j * 64 + tid];
-          Xs[i * 64 + tid] = (s0 + s1) * rdiag[i];
         }
+#pragma unroll
+        for (int u = 0; u < TB; ++u)
+          if (b0 + u < b1) Xs[(b0 + u) * 64 + tid] = xr[u];
       }
       __syncthreads();
       // rows below the block: thread owns column c = tid & 63 and rows
@@ -1122,6 +1139,95 @@ __global__ __launch_bounds__(256) void k_trsm(const Bufs* __restrict__ bufs, con
     for (int e = tid; e < p * 64; e += 256) {
       int i = e % p, c = e / p;
       if (c < cw) X[i + (size_t)(J.c0 + c) * ldx] = Xs[i * 64 + c];
+    }
+  }
+}
+
+// X <- L X with L the stored inverse of a diagonal leaf factor (lower
+// triangular, p <= 128) and X a panel of up to 64 columns (layout 0: col-major;
+// layout 1: X^T stored).  No dependency chain: thread (tr, tc) accumulates
+// rows tr + 16a (a < 8) of columns 4 tc .. 4 tc + 3 over k = 0 .. i.
+__global__ __launch_bounds__(256) void k_trmm(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
+                                              const TrsmJob* __restrict__ jobs, int j0) {
+  const TrsmJob J = jobs[j0 + blockIdx.x];
+  const int nc = dimv(dyn, J.ncols);
+  const int cw = min(J.cw, nc - J.c0);
+  if (cw <= 0) return;
+  extern __shared__ double smem[];
+  const int p = J.p;
+  double* Lp = smem;                       // packed lower: row i at i(i+1)/2
+  double* Xs = smem + LF * (LF + 1) / 2;   // p x 64 row-major
+  const double* __restrict__ L = refp(bufs, J.L);
+  const int ldl = J.L.ld;
+  const int tid = threadIdx.x;
+  for (int base = 0; base < p * p; base += 2048) {
+    double r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int i = e % p, j = e / p;
+      r[u] = (e < p * p && i >= j) ? L[i + (size_t)j * ldl] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int i = e % p, j = e / p;
+      if (e < p * p && i >= j) Lp[i * (i + 1) / 2 + j] = r[u];
+    }
+  }
+  double* __restrict__ X = refp(bufs, J.X);
+  const int ldx = J.X.ld;
+  for (int base = 0; base < p * 64; base += 2048) {
+    double r[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int c = (J.layout == 1) ? (e & 63) : (e / p), i = (J.layout == 1) ? (e >> 6) : (e % p);
+      r[u] = (e < p * 64 && c < cw) ? (J.layout == 1 ? X[(J.c0 + c) + (size_t)i * ldx] : X[i + (size_t)(J.c0 + c) * ldx])
+                                    : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      int e = base + u * 256 + tid;
+      int c = (J.layout == 1) ? (e & 63) : (e / p), i = (J.layout == 1) ? (e >> 6) : (e % p);
+      if (e < p * 64) Xs[i * 64 + c] = (c < cw) ? r[u] : 0.0;
+    }
+  }
+  __syncthreads();
+  const int tr = tid & 15, tc = tid >> 4;
+  double acc[8][4];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  if (4 * tc < cw) {
+    for (int k = 0; k < p; ++k) {
+      double xb[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) xb[b] = Xs[k * 64 + 4 * tc + b];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int i = tr + 16 * a;
+        if (i >= k && i < p) {
+          const double l = Lp[i * (i + 1) / 2 + k];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = fma(l, xb[b], acc[a][b]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int i = tr + 16 * a;
+    if (i >= p) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int c = 4 * tc + b;
+      if (c >= cw) continue;
+      if (J.layout == 1)
+        X[(J.c0 + c) + (size_t)i * ldx] = acc[a][b];
+      else
+        X[i + (size_t)(J.c0 + c) * ldx] = acc[a][b];
     }
   }
 }
@@ -1400,6 +1506,8 @@ hipError_t setup_kernel_attributes() {
   e = hipFuncSetAttribute((const void*)k_leaf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_LEAF);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_trsm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_TRSM);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_trmm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_TRSM);
   return e;
 }
 
@@ -1424,6 +1532,9 @@ hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st) {
       break;
     case ST_TRSM:
       if (n > 0) k_trsm<<<n, 256, LDS_TRSM, st>>>(L.dbufs, L.dyn, L.trsms, s.begin);
+      break;
+    case ST_TRMM:
+      if (n > 0) k_trmm<<<n, 256, LDS_TRSM, st>>>(L.dbufs, L.dyn, L.trsms, s.begin);
       break;
     case ST_COPY_RANK:
       if (L.n_copy > 0) k_copy_rank<<<(L.n_copy + 255) / 256, 256, 0, st>>>(L.dyn, L.copy_pairs, L.n_copy);

@@ -175,7 +175,10 @@ class Builder {
     for (int32_t j = 0; j < nj; ++j) {
       GemmJob& g = P.gjobs[job_base + j];
       g.p0 = int32_t(P.gprods.size());
-      for (auto& p : pending_prods[j]) P.gprods.push_back(p);
+      for (auto& p : pending_prods[j]) {
+        P.gprods.push_back(p);
+        if (p.A.buf == B_RHS || p.B.buf == B_RHS) g.fp32 = 0;   // the solve stays FP64
+      }
       g.p1 = int32_t(P.gprods.size());
       int mt = (g.m.maxv + TM - 1) / TM, nt = (g.n.maxv + TN - 1) / TN;
       for (int a = 0; a < mt; ++a)
@@ -621,11 +624,12 @@ class Builder {
   }
 
   // ---------------------------------------------------------------- the sweep
-  // triangular-solve jobs X <- L_jj^{-1} X (in 64-column chunks)
-  void add_trsm(int64_t j, Ref X, int layout, Dim nc) {
+  // jobs X <- L_jj^{-1} X in 64-column chunks: by substitution with L_jj
+  // (inverse = false) or by multiplication with the stored inverse
+  void add_trsm(int64_t j, Ref X, int layout, Dim nc, bool inverse = false) {
     const BlockInfo& Dg = P.blocks[P.diag_block[j]];
     const int pj = int(Dg.r1 - Dg.r0);
-    Ref Lr{B_DENSE, pj, Dg.off_d};
+    Ref Lr = inverse ? Ref{B_LINV, pj, P.linv_off[j]} : Ref{B_DENSE, pj, Dg.off_d};
     for (int c0 = 0; c0 < nc.maxv; c0 += 64)
       P.trsms.push_back(TrsmJob{Lr, pj, layout, X, nc, c0, std::min(64, nc.maxv - c0)});
   }
@@ -653,21 +657,26 @@ class Builder {
     int32_t l0 = int32_t(P.leafs.size());
     P.leafs.push_back(J);
     st.push_back(Stage{ST_LEAF, l0, l0 + 1, 1});
-    const int64_t cj0 = lo(P.D, j);
+    // L_jj^{-1} into B_LINV (substitution on the identity), then the
+    // second lane's right-hand sides by multiplication with it
     int32_t t0 = int32_t(P.trsms.size());
+    add_trsm(j, Ref{B_LINV, J.p, P.linv_off[j]}, 3, dim_static(J.p));
+    st.push_back(Stage{ST_TRSM, t0, int32_t(P.trsms.size()), 1});
+    const int64_t cj0 = lo(P.D, j);
+    t0 = int32_t(P.trsms.size());
     for (auto& dt : dns) {
       const BlockInfo& T = P.blocks[dt.first];
       if (T.a == T.c) continue;
-      add_trsm(j, Ref{B_DENSE, int32_t(T.r1 - T.r0), T.off_d}, 1, dim_static(int(T.r1 - T.r0)));
+      add_trsm(j, Ref{B_DENSE, int32_t(T.r1 - T.r0), T.off_d}, 1, dim_static(int(T.r1 - T.r0)), true);
     }
     for (int32_t b : active[j]) {
       if (std::find(fresh.begin(), fresh.end(), b) != fresh.end()) continue;
       const BlockInfo& T = P.blocks[b];
-      add_trsm(j, Ref{B_V, int32_t(T.c1 - T.c0), T.off_v + (cj0 - T.c0)}, 0, rank_dim(b));
+      add_trsm(j, Ref{B_V, int32_t(T.c1 - T.c0), T.off_v + (cj0 - T.c0)}, 0, rank_dim(b), true);
     }
-    if (fuse_rhs) add_trsm(j, Ref{B_RHS, int32_t(P.rhs_ld), cj0}, 0, dim_static(1));
+    if (fuse_rhs) add_trsm(j, Ref{B_RHS, int32_t(P.rhs_ld), cj0}, 0, dim_static(1), true);
     int32_t t1 = int32_t(P.trsms.size());
-    if (t1 > t0) st.push_back(Stage{ST_TRSM, t0, t1, 1});
+    if (t1 > t0) st.push_back(Stage{ST_TRMM, t0, t1, 1});
   }
 
   void build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps);
@@ -905,10 +914,10 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
       int32_t t0 = int32_t(P.trsms.size());
       for (auto& t : lrs) {
         const BlockInfo& B = P.blocks[t.b];
-        add_trsm(j, Ref{B_V, int32_t(B.c1 - B.c0), B.off_v + (cj0 - B.c0)}, 0, rank_dim(t.b));
+        add_trsm(j, Ref{B_V, int32_t(B.c1 - B.c0), B.off_v + (cj0 - B.c0)}, 0, rank_dim(t.b), true);
       }
       int32_t t1 = int32_t(P.trsms.size());
-      if (t1 > t0) st.push_back(Stage{ST_TRSM, t0, t1});
+      if (t1 > t0) st.push_back(Stage{ST_TRMM, t0, t1});
     }
 
     // ---- sibling update: the ancestor t1 whose last leaf is c_j, a left son
@@ -1032,10 +1041,12 @@ void Builder::build_solves() {
     scr_top = 0;
     int64_t c0 = lo(D, j);
     int pj = int(hi(D, j) - c0);
+    // the same arithmetic as the solve fused into the factorisation sweep:
+    // multiplication by the stored inverse of L_jj
     int32_t t0 = int32_t(P.trsms.size());
-    P.trsms.push_back(TrsmJob{Ref{B_DENSE, pj, P.blocks[P.diag_block[j]].off_d}, pj, 0,
-                              Ref{B_RHS, int32_t(P.rhs_ld), c0}, dim_static(1), 0, 1});
-    st.push_back(Stage{ST_TRSM, t0, t0 + 1});
+    P.trsms.push_back(TrsmJob{Ref{B_LINV, pj, P.linv_off[j]}, pj, 0, Ref{B_RHS, int32_t(P.rhs_ld), c0},
+                              dim_static(1), 0, 1});
+    st.push_back(Stage{ST_TRMM, t0, t0 + 1});
     int lv = D;
     int64_t node = j;
     while (lv >= 1 && (node & 1) == 1) {
@@ -1237,6 +1248,12 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
   }
   for (int64_t i = 0; i < m; ++i)
     if (P.diag_block[i] < 0) return "missing diagonal leaf";
+  P.linv_off.resize(m);
+  for (int64_t i = 0; i < m; ++i) {
+    const int64_t pj = P.lo[D][i + 1] - P.lo[D][i];
+    P.linv_off[i] = P.linv_elems;
+    P.linv_elems += pj * pj;
+  }
   P.rhs_ld = n;
   P.omega_rows = std::max<int64_t>(n, 1);
   Builder Bd(P);

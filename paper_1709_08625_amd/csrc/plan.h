@@ -23,7 +23,8 @@ enum BufId : int32_t {
   B_OMEGA = 4,   // fixed Gaussian test matrix (Nmax x rcap col-major)
   B_RHS = 5,     // right-hand side solved inside the sweep (cluster order)
   B_PERS = 6,    // persistent scratch (assembly, R factors, coefficients)
-  B_COUNT = 7
+  B_LINV = 7,    // inverses of the diagonal leaf factors (p x p col-major per leaf)
+  B_COUNT = 8
 };
 
 struct Ref {
@@ -118,6 +119,10 @@ struct LeafJob {
 
 // ---------------------------------------------------------------- trsm jobs
 // X <- L^{-1} X for a panel of right-hand sides, L lower triangular p x p.
+// Layout 3 forms the inverse: columns [c0, c0+cw) of X <- L^{-1} (X p x p
+// col-major, the identity is generated in place of a load).  The same job
+// record drives the multiplication stage ST_TRMM, X <- L X with L the stored
+// inverse (layouts 0 and 1 only).
 // layout 0: X is p x ncols col-major (ld); layout 1: X^T is stored, i.e.
 // element (i, c) of X is at X[c + i*ld] (dense target solved from the right).
 struct TrsmJob {
@@ -134,7 +139,7 @@ struct TrsmJob {
 // ST_FORK: the second lane (stream) waits for the work issued so far on the
 // first; ST_JOIN: the first lane waits for the work issued on the second.
 enum StageKind : int32_t { ST_GEMM = 0, ST_TSQR_SEG, ST_TSQR_RED, ST_SMALL, ST_LEAF, ST_TRSM, ST_COPY_RANK,
-                           ST_FORK, ST_JOIN };
+                           ST_FORK, ST_JOIN, ST_TRMM };
 struct Stage {
   int32_t kind;
   int32_t begin, end;   // item range in the kind's array (tiles for GEMM)
@@ -160,7 +165,8 @@ struct Plan {
   std::vector<BlockInfo> blocks;
   std::unordered_map<uint64_t, int32_t> status;   // (l,a,c) -> block id, or -1 = subdivided
   std::vector<int32_t> diag_block;                // leaf j -> block id of (j, j)
-  int64_t dense_elems = 0, u_elems = 0, v_elems = 0;
+  int64_t dense_elems = 0, u_elems = 0, v_elems = 0, linv_elems = 0;
+  std::vector<int64_t> linv_off;                  // leaf j -> offset of its inverse in B_LINV
   int32_t n_dyn = 0;                               // dynamic dimension slots
 
   // executable job arrays (all steps share them; stages index into them)

@@ -114,7 +114,7 @@ EXPORTS = ["hcov_opts_default", "hcov_build", "hcov_set_theta", "hcov_cholesky",
 
 EAGAIN = -7
 
-STAGE_KINDS = {"gemm": 0, "tsqr_seg": 1, "tsqr_red": 2, "small": 3, "leaf": 4, "trsm": 5}
+STAGE_KINDS = {"gemm": 0, "tsqr_seg": 1, "tsqr_red": 2, "small": 3, "leaf": 4, "trsm": 5, "trmm": 9}
 
 
 class HcovError(RuntimeError):
