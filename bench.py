@@ -133,6 +133,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-kind", default="gemm")
     ap.add_argument("--workload", default="loglik512k", choices=["loglik512k", "serving"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--requests", type=int, default=96)
     ap.add_argument("--slots", type=int, default=6)
     args = ap.parse_args()
@@ -156,7 +157,8 @@ def main():
     locs, xi = workloads.uniform(n, seed=0)
     stream = torch.cuda.current_stream().cuda_stream
     t_build = time.perf_counter()
-    H = hcov.HCov(locs, theta0, eps=eps, leaf=leaf, eta=eta, stream=stream)
+    opts = {"precision": hcov.MIXED if args.precision == "mixed" else hcov.FP64}
+    H = hcov.HCov(locs, theta0, eps=eps, leaf=leaf, eta=eta, stream=stream, opts=opts)
     t_build = time.perf_counter() - t_build
     progress(f"trees, plan and first assembly at n={n}: {t_build:.1f} s")
     # synthetic observations: a sample Z = L~ xi of the field at theta0
@@ -205,12 +207,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {
             "workload": f"matern-loglik n={n} uniform[0,1]^2 seed 0, theta=(sigma2 1, ell 0.08, nu 0.8, "
-                        f"nugget 1e-4) +-10% per step, leaf {leaf}, eta {eta}, eps {eps}, FP64 H path",
-            "n": n, "leaf": leaf, "eta": eta, "eps": eps, "precision": "fp64",
+                        f"nugget 1e-4) +-10% per step, leaf {leaf}, eta {eta}, eps {eps}, "
+                        f"{'FP64' if args.precision == 'fp64' else 'mixed-precision'} H path",
+            "n": n, "leaf": leaf, "eta": eta, "eps": eps, "precision": args.precision,
         },
         "latency_ms": {"p50": 1e3 * float(np.percentile(lat, 50)), "p99": 1e3 * float(np.percentile(lat, 99)),
                        "mean": 1e3 * float(np.mean(lat))},

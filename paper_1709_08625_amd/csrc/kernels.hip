@@ -430,6 +430,87 @@ __device__ void jacobi_svd_lds(double* A, double* V, int n, double thr2, double*
   }
 }
 
+// Single-wave variant for n <= 64: the whole round-robin round is done by
+// the first wave (g = 64 / pairs lanes per pair, rounded down to a power of
+// two) with wave-scope ordering of the LDS traffic instead of work-group
+// barriers between rounds; the other waves only join at the end.
+__device__ void jacobi_svd_wave(double* A, double* V, int n, double thr2, double* red) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < n * n; e += 256) {
+    int i = e % n, j = e / n;
+    V[i + j * SM] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const int np = (n + 1) & ~1;
+    const int npairs = np / 2;
+    int g = 64;
+    while (g > 1 && npairs * g > 64) g >>= 1;
+    const int grp = tid / g, gl = tid % g;
+    const double tol = fmax(1e-14, 8.0 * 2.220446049250313e-16 * n);
+    const double tol2 = tol * tol;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      double off2 = 0.0;
+      for (int rnd = 0; rnd < np - 1; ++rnd) {
+        if (grp < npairs) {
+          int a, b;
+          if (grp == 0) {
+            a = np - 1;
+            b = rnd;
+          } else {
+            a = (rnd + grp) % (np - 1);
+            b = (rnd - grp + (np - 1)) % (np - 1);
+          }
+          if (a < n && b < n) {
+            const int pp = min(a, b), qq = max(a, b);
+            double* __restrict__ Ap = A + pp * SM;
+            double* __restrict__ Aq = A + qq * SM;
+            double al = 0.0, be = 0.0, ga = 0.0;
+            for (int i = gl; i < n; i += g) {
+              const double x = Ap[i], y = Aq[i];
+              al = fma(x, x, al);
+              be = fma(y, y, be);
+              ga = fma(x, y, ga);
+            }
+            for (int o = g >> 1; o > 0; o >>= 1) {
+              al += __shfl_xor(al, o);
+              be += __shfl_xor(be, o);
+              ga += __shfl_xor(ga, o);
+            }
+            if (ga != 0.0 && al != 0.0 && be != 0.0 && (al >= thr2 || be >= thr2)) {
+              const double g2 = ga * ga, ab = al * be;
+              off2 = fmax(off2, g2 / ab);
+              if (g2 >= tol2 * ab) {
+                const double d = be - al;
+                const double h = sqrt(fma(d, d, 4.0 * g2));
+                const double tt = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + h);
+                const double cs = 1.0 / sqrt(fma(tt, tt, 1.0));
+                const double sn = cs * tt;
+                double* __restrict__ Vp = V + pp * SM;
+                double* __restrict__ Vq = V + qq * SM;
+                for (int i = gl; i < n; i += g) {
+                  const double x = Ap[i], y = Aq[i], vx = Vp[i], vy = Vq[i];
+                  Ap[i] = cs * x - sn * y;
+                  Aq[i] = sn * x + cs * y;
+                  Vp[i] = cs * vx - sn * vy;
+                  Vq[i] = sn * vx + cs * vy;
+                }
+              }
+            }
+          }
+        }
+        // the next round reads columns written by other lanes of this wave
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
+      for (int o = 32; o > 0; o >>= 1) off2 = fmax(off2, __shfl_xor(off2, o));
+      if (off2 < tol2) break;
+    }
+  }
+  __syncthreads();
+}
+
 // Squared Frobenius norm of the n x n matrix A in LDS, returned to every
 // thread (uses red[4..7]).
 __device__ double fro2_lds(const double* A, int n, double* red) {
@@ -743,7 +824,10 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
   {
     const double f2 = fro2_lds(A, n, red);
     const double dt = 1e-3 * eps;
-    jacobi_svd_lds(A, V, n, dt * dt * f2, red);
+    if (n <= 64)
+      jacobi_svd_wave(A, V, n, dt * dt * f2, red);
+    else
+      jacobi_svd_lds(A, V, n, dt * dt * f2, red);
   }
   __syncthreads();
   order_desc(A, n, sv, ord);

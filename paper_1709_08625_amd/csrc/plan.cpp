@@ -53,6 +53,7 @@ class Builder {
   Plan& P;
   // per-step scratch bump allocator
   int64_t scr_top = 0;
+  int32_t cur_lane = 0;   // lane of the stages emitted next
   int32_t dyn_base = 0, dyn_top = 0, dyn_max = 0;
   // current stage buffers (one step at a time)
   struct GemmStage {
@@ -187,7 +188,7 @@ class Builder {
     pending_prods.clear();
     job_base = int32_t(P.gjobs.size());
     int32_t t1 = int32_t(P.gtiles.size());
-    if (t1 > t0) out.push_back(Stage{ST_GEMM, t0, t1});
+    if (t1 > t0) out.push_back(Stage{ST_GEMM, t0, t1, cur_lane});
   }
 
   // ---------------------------------------------------------------- TSQR
@@ -757,7 +758,7 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         int64_t p, q;
         Dim r;          // sketch width
         Dim rk;         // kept directions of Y
-        int64_t y, qm, bp, ry, rq, rb, pm, c2;
+        int64_t y, qm, bp, ry, rq, rb, pm, c2, bpp;
         std::vector<int64_t> p1, z1;
       };
       std::vector<SK> sk(lrs.size());
@@ -870,6 +871,23 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         }
       }
       emit(listB, st);
+      // second lane, once B' exists: B''_t = L_jj^{-1} B'_t on the leaf-j rows
+      // (the first rows of every target that starts at j), while this lane
+      // computes R_Q, R_B' and the truncation
+      st.push_back(Stage{ST_FORK, 0, 0});
+      {
+        const BlockInfo& Dg = P.blocks[P.diag_block[j]];
+        const int pd = int(Dg.r1 - Dg.r0);
+        for (auto& s2 : sk) {
+          s2.bpp = scr_alloc(int64_t(pd) * s2.r.maxv);
+          int32_t d = defer(listA, Ref{B_SCR, pd, s2.bpp}, dim_static(pd), s2.rk, 1);
+          dprod(listA[d], Ref{B_LINV, pd, P.linv_off[j]}, 0, Ref{B_SCR, int32_t(s2.q), s2.bp}, 0,
+                dim_static(pd), 0, 0, dim_static(pd), s2.rk, 1.0);
+        }
+        cur_lane = 1;
+        emit(listA, st);
+        cur_lane = 0;
+      }
       // R_Q and R_B'
       for (auto& s : sk) {
         tsqr(Ref{B_SCR, int32_t(s.p), s.qm}, s.p, s.rk, Ref{B_SCR, RM, s.rq});
@@ -892,7 +910,10 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         P.smalls.push_back(J);
       }
       flush_small(st, sm0);
-      // U := Q C2, V := B' C2
+      // U := Q C2, V := B' C2 with the leaf-j rows of V from B'' (already
+      // multiplied by L_jj^{-1}: the second lane joins first)
+      st.push_back(Stage{ST_JOIN, 0, 0});
+      const int pdj = int(cj1 - cj0);
       for (auto& s : sk) {
         const BlockInfo& B = P.blocks[s.b];
         int32_t d = defer(listA, Ref{B_U, int32_t(s.p), B.off_u}, dim_static(int(s.p)),
@@ -901,24 +922,17 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
               dim_static(int(s.p)), rank_dim(s.b), 1.0);
         int32_t d2 = defer(listA, Ref{B_V, int32_t(s.q), B.off_v}, dim_static(int(s.q)),
                            rank_dim(s.b), 1);
-        dprod(listA[d2], Ref{B_SCR, int32_t(s.q), s.bp}, 0, Ref{B_SCR, RM, s.c2}, 0, s.rk, 0, 0,
-              dim_static(int(s.q)), rank_dim(s.b), 1.0);
+        dprod(listA[d2], Ref{B_SCR, pdj, s.bpp}, 0, Ref{B_SCR, RM, s.c2}, 0, s.rk, 0, 0,
+              dim_static(pdj), rank_dim(s.b), 1.0);
+        if (s.q > pdj)
+          dprod(listA[d2], Ref{B_SCR, int32_t(s.q), s.bp + pdj}, 0, Ref{B_SCR, RM, s.c2}, 0, s.rk,
+                pdj, 0, dim_static(int(s.q) - pdj), rank_dim(s.b), 1.0);
       }
       emit(listA, st);
     }
 
-    // ---- second lane joins; then the leaf-j rows of the low-rank targets
-    // that started at j (their V was produced by the recompression above)
-    st.push_back(Stage{ST_JOIN, 0, 0});
-    {
-      int32_t t0 = int32_t(P.trsms.size());
-      for (auto& t : lrs) {
-        const BlockInfo& B = P.blocks[t.b];
-        add_trsm(j, Ref{B_V, int32_t(B.c1 - B.c0), B.off_v + (cj0 - B.c0)}, 0, rank_dim(t.b), true);
-      }
-      int32_t t1 = int32_t(P.trsms.size());
-      if (t1 > t0) st.push_back(Stage{ST_TRMM, t0, t1});
-    }
+    // ---- without low-rank targets the second lane joins here
+    if (lrs.empty()) st.push_back(Stage{ST_JOIN, 0, 0});
 
     // ---- sibling update: the ancestor t1 whose last leaf is c_j, a left son
     {
