@@ -33,10 +33,25 @@ namespace hc {
 constexpr int GT = 64, GK = 32;
 constexpr int GR = GK * GT / 256;   // elements of each operand chunk per thread
 
+// Products of a job, resolved once per batch into LDS: operand base
+// pointers, leading dimensions, live dimensions and the intersection with
+// the tile.  This replaces the per-product chain of dependent loads
+// (descriptor -> dynamic dimensions -> buffer table -> data).
+constexpr int PBATCH = 32;
+struct ProdMeta {
+  const double* A;
+  const double* B;
+  double alpha;
+  int lda, ldb, k;
+  int pr0, pr1, pc0, pc1;
+  int ta, tb;
+  int live;
+};
+
 template <class T, int NX, int NY>
 __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const int* __restrict__ dyn, const GemmJob& J,
                                           const GemmProd* __restrict__ prods, int m, int n, int r0,
-                                          int c0, T (*As)[GT + 1], T (*Bs)[GT + 1]) {
+                                          int c0, T (*As)[GT + 1], T (*Bs)[GT + 1], ProdMeta* pm) {
   const int tid = threadIdx.x;
   const int ty = tid & 15, tx = tid >> 4;   // rows follow the lane index (coalesced C and tb==2 access)
   T acc[NX][NY];
@@ -45,89 +60,122 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
 #pragma unroll
     for (int b = 0; b < NY; ++b) acc[a][b] = T(0);
 
-  for (int pi = J.p0; pi < J.p1; ++pi) {
-    const GemmProd Pd = prods[pi];
-    const int k = dimv(dyn, Pd.k);
-    int mi = dimv(dyn, Pd.mi), nj = dimv(dyn, Pd.nj);
-    if (k <= 0 || mi <= 0 || nj <= 0) continue;
-    // product rows [Pd.i0, Pd.i0+mi) intersect tile rows [r0, r0+GT)
-    const int pr0 = Pd.i0, pr1 = min(Pd.i0 + mi, m), pc0 = Pd.j0, pc1 = min(Pd.j0 + nj, n);
-    if (pr1 <= r0 || pr0 >= r0 + GT || pc1 <= c0 || pc0 >= c0 + GT) continue;
-    const double* __restrict__ A = refp(bufs, Pd.A);
-    const double* __restrict__ B = refp(bufs, Pd.B);
-    const int lda = Pd.A.ld, ldb = Pd.B.ld;
-    const double alpha = Pd.alpha;
-    if (Pd.tb == 2) {
-      // C += alpha * A (element-wise; partial sums of a split job)
+  // element e of a chunk: A chunk is GT x GK, B chunk GK x GT; the index
+  // split follows the operand's storage order so that lanes coalesce
+  T ra[GR], rb[GR];
+  auto fetch = [&](const ProdMeta& M, int k0) {
+#pragma unroll
+    for (int r = 0; r < GR; ++r) {
+      int e = tid + 256 * r;
+      int ii = M.ta == 0 ? (e & (GT - 1)) : (e / GK);
+      int kk = M.ta == 0 ? (e / GT) : (e & (GK - 1));
+      int gi = r0 + ii, gk = k0 + kk;
+      double v = 0.0;
+      if (gi >= M.pr0 && gi < M.pr1 && gk < M.k) {
+        int li = gi - M.pr0;
+        v = M.ta == 0 ? M.A[li + (size_t)gk * M.lda] : M.A[gk + (size_t)li * M.lda];
+      }
+      ra[r] = T(M.alpha * v);
+    }
+#pragma unroll
+    for (int r = 0; r < GR; ++r) {
+      int e = tid + 256 * r;
+      int kk = M.tb == 0 ? (e & (GK - 1)) : (e / GT);
+      int jj = M.tb == 0 ? (e / GK) : (e & (GT - 1));
+      int gj = c0 + jj, gk = k0 + kk;
+      double v = 0.0;
+      if (gj >= M.pc0 && gj < M.pc1 && gk < M.k) {
+        int lj = gj - M.pc0;
+        v = M.tb == 0 ? M.B[gk + (size_t)lj * M.ldb] : M.B[lj + (size_t)gk * M.ldb];
+      }
+      rb[r] = T(v);
+    }
+  };
+  const ProdMeta* pmc = pm;
+  auto stash = [&](int ta, int tb) {
+#pragma unroll
+    for (int r = 0; r < GR; ++r) {
+      int e = tid + 256 * r;
+      int ii = ta == 0 ? (e & (GT - 1)) : (e / GK);
+      int kk = ta == 0 ? (e / GT) : (e & (GK - 1));
+      As[kk][ii] = ra[r];
+      int k2 = tb == 0 ? (e & (GK - 1)) : (e / GT);
+      int jj = tb == 0 ? (e / GK) : (e & (GT - 1));
+      Bs[k2][jj] = rb[r];
+    }
+  };
+
+  for (int base = J.p0; base < J.p1; base += PBATCH) {
+    const int cnt = min(PBATCH, J.p1 - base);
+    __syncthreads();   // the previous batch is consumed
+    if (tid < cnt) {
+      const GemmProd Pd = prods[base + tid];
+      ProdMeta M;
+      M.k = dimv(dyn, Pd.k);
+      const int mi = dimv(dyn, Pd.mi), nj = dimv(dyn, Pd.nj);
+      M.pr0 = Pd.i0;
+      M.pr1 = min(Pd.i0 + mi, m);
+      M.pc0 = Pd.j0;
+      M.pc1 = min(Pd.j0 + nj, n);
+      M.live = (M.k > 0 && mi > 0 && nj > 0 && M.pr1 > r0 && M.pr0 < r0 + GT && M.pc1 > c0 && M.pc0 < c0 + GT) ? 1 : 0;
+      M.A = refp(bufs, Pd.A);
+      M.B = refp(bufs, Pd.B);
+      M.lda = Pd.A.ld;
+      M.ldb = Pd.B.ld;
+      M.alpha = Pd.alpha;
+      M.ta = Pd.ta;
+      M.tb = Pd.tb;
+      pm[tid] = M;
+    }
+    __syncthreads();
+    // element-wise additions of partial sums (tb == 2)
+    for (int q = 0; q < cnt; ++q) {
+      const ProdMeta& M = pmc[q];
+      if (!M.live || M.tb != 2) continue;
 #pragma unroll
       for (int x = 0; x < NX; ++x)
 #pragma unroll
         for (int y = 0; y < NY; ++y) {
           int gi = r0 + ty + 16 * x, gj = c0 + tx + 16 * y;
-          if (gi >= pr0 && gi < pr1 && gj >= pc0 && gj < pc1)
-            acc[x][y] += T(alpha * A[(gi - pr0) + (size_t)(gj - pc0) * lda]);
+          if (gi >= M.pr0 && gi < M.pr1 && gj >= M.pc0 && gj < M.pc1)
+            acc[x][y] += T(M.alpha * M.A[(gi - M.pr0) + (size_t)(gj - M.pc0) * M.lda]);
         }
-      continue;
     }
-    // element e of a chunk: A chunk is GT x GK, B chunk GK x GT; the index
-    // split follows the operand's storage order so that lanes coalesce
-    T ra[GR], rb[GR];
-    auto fetch = [&](int k0) {
-#pragma unroll
-      for (int r = 0; r < GR; ++r) {
-        int e = tid + 256 * r;
-        int ii = Pd.ta == 0 ? (e & (GT - 1)) : (e / GK);
-        int kk = Pd.ta == 0 ? (e / GT) : (e & (GK - 1));
-        int gi = r0 + ii, gk = k0 + kk;
-        double v = 0.0;
-        if (gi >= pr0 && gi < pr1 && gk < k) {
-          int li = gi - pr0;
-          v = Pd.ta == 0 ? A[li + (size_t)gk * lda] : A[gk + (size_t)li * lda];
-        }
-        ra[r] = T(alpha * v);
-      }
-#pragma unroll
-      for (int r = 0; r < GR; ++r) {
-        int e = tid + 256 * r;
-        int kk = Pd.tb == 0 ? (e & (GK - 1)) : (e / GT);
-        int jj = Pd.tb == 0 ? (e / GK) : (e & (GT - 1));
-        int gj = c0 + jj, gk = k0 + kk;
-        double v = 0.0;
-        if (gj >= pc0 && gj < pc1 && gk < k) {
-          int lj = gj - pc0;
-          v = Pd.tb == 0 ? B[gk + (size_t)lj * ldb] : B[lj + (size_t)gk * ldb];
-        }
-        rb[r] = T(v);
-      }
+    // products: (product, k-chunk) pairs in order, the next pair's global
+    // loads in flight while the current one is consumed from LDS
+    auto next_live = [&](int q) {
+      while (q < cnt && (!pmc[q].live || pmc[q].tb == 2)) ++q;
+      return q;
     };
-    fetch(0);
-    for (int k0 = 0; k0 < k; k0 += GK) {
-#pragma unroll
-      for (int r = 0; r < GR; ++r) {
-        int e = tid + 256 * r;
-        int ii = Pd.ta == 0 ? (e & (GT - 1)) : (e / GK);
-        int kk = Pd.ta == 0 ? (e / GT) : (e & (GK - 1));
-        As[kk][ii] = ra[r];
-        int k2 = Pd.tb == 0 ? (e & (GK - 1)) : (e / GT);
-        int jj = Pd.tb == 0 ? (e / GK) : (e & (GT - 1));
-        Bs[k2][jj] = rb[r];
-      }
+    int q = next_live(0);
+    if (q >= cnt) continue;
+    int k0 = 0;
+    fetch(pmc[q], 0);
+    while (q < cnt) {
+      if (k0 > 0 || q > 0) __syncthreads();   // LDS tiles of the previous pair consumed
+      stash(pmc[q].ta, pmc[q].tb);
       __syncthreads();
-      if (k0 + GK < k) fetch(k0 + GK);
-      const int kl = min(GK, k - k0);
+      int nq = q, nk0 = k0 + GK;
+      if (nk0 >= pmc[q].k) {
+        nq = next_live(q + 1);
+        nk0 = 0;
+      }
+      if (nq < cnt) fetch(pmc[nq], nk0);
+      const int kl = min(GK, pmc[q].k - k0);
 #pragma unroll 8
       for (int kk = 0; kk < kl; ++kk) {
         T av[NX], bv[NY];
 #pragma unroll
-        for (int q = 0; q < NX; ++q) av[q] = As[kk][ty + 16 * q];
+        for (int z = 0; z < NX; ++z) av[z] = As[kk][ty + 16 * z];
 #pragma unroll
-        for (int q = 0; q < NY; ++q) bv[q] = Bs[kk][tx + 16 * q];
+        for (int z = 0; z < NY; ++z) bv[z] = Bs[kk][tx + 16 * z];
 #pragma unroll
         for (int x = 0; x < NX; ++x)
 #pragma unroll
           for (int y = 0; y < NY; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
       }
-      __syncthreads();
+      q = nq;
+      k0 = nk0;
     }
   }
   double* __restrict__ C = refp(bufs, J.C);
@@ -157,6 +205,7 @@ __global__ __launch_bounds__(256) void k_gemm(const Bufs* __restrict__ bufs, con
   if (r0 >= m || c0 >= n) return;
   __shared__ double As[GK][GT + 1];
   __shared__ double Bs[GK][GT + 1];
+  __shared__ ProdMeta pm[PBATCH];
   const int er = min(GT, m - r0), ec = min(GT, n - c0);
   const int nx = er <= 16 ? 1 : (er <= 32 ? 2 : 4), ny = ec <= 16 ? 1 : (ec <= 32 ? 2 : 4);
   if (J.fp32) {
@@ -164,28 +213,28 @@ __global__ __launch_bounds__(256) void k_gemm(const Bufs* __restrict__ bufs, con
     float(*Af)[GT + 1] = reinterpret_cast<float(*)[GT + 1]>(&As[0][0]);
     float(*Bf)[GT + 1] = reinterpret_cast<float(*)[GT + 1]>(&Bs[0][0]);
     switch (nx * 8 + ny) {
-      case 9: gemm_tile<float, 1, 1>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
-      case 10: gemm_tile<float, 1, 2>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
-      case 12: gemm_tile<float, 1, 4>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
-      case 17: gemm_tile<float, 2, 1>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
-      case 18: gemm_tile<float, 2, 2>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
-      case 20: gemm_tile<float, 2, 4>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
-      case 33: gemm_tile<float, 4, 1>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
-      case 34: gemm_tile<float, 4, 2>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
-      default: gemm_tile<float, 4, 4>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf); break;
+      case 9: gemm_tile<float, 1, 1>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf, pm); break;
+      case 10: gemm_tile<float, 1, 2>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf, pm); break;
+      case 12: gemm_tile<float, 1, 4>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf, pm); break;
+      case 17: gemm_tile<float, 2, 1>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf, pm); break;
+      case 18: gemm_tile<float, 2, 2>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf, pm); break;
+      case 20: gemm_tile<float, 2, 4>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf, pm); break;
+      case 33: gemm_tile<float, 4, 1>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf, pm); break;
+      case 34: gemm_tile<float, 4, 2>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf, pm); break;
+      default: gemm_tile<float, 4, 4>(bufs, dyn, J, prods, m, n, r0, c0, Af, Bf, pm); break;
     }
     return;
   }
   switch (nx * 8 + ny) {
-    case 9: gemm_tile<double, 1, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 10: gemm_tile<double, 1, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 12: gemm_tile<double, 1, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 17: gemm_tile<double, 2, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 18: gemm_tile<double, 2, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 20: gemm_tile<double, 2, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 33: gemm_tile<double, 4, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    case 34: gemm_tile<double, 4, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
-    default: gemm_tile<double, 4, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs); break;
+    case 9: gemm_tile<double, 1, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
+    case 10: gemm_tile<double, 1, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
+    case 12: gemm_tile<double, 1, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
+    case 17: gemm_tile<double, 2, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
+    case 18: gemm_tile<double, 2, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
+    case 20: gemm_tile<double, 2, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
+    case 33: gemm_tile<double, 4, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
+    case 34: gemm_tile<double, 4, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
+    default: gemm_tile<double, 4, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
   }
 }
 
@@ -318,6 +367,15 @@ __global__ __launch_bounds__(256) void k_tsqr_red(const Bufs* __restrict__ bufs,
 }
 
 // ------------------------------------------------------------------ small SVD
+// Orders a wave's LDS stores before its later loads from other lanes (a
+// wave executes its LDS instructions in order; this keeps the compiler from
+// moving them and waits for completion).
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One-sided Jacobi (Hestenes) on the columns of an n x n matrix A in LDS
 // (ld = SM), accumulating the right rotations in V: A V = U S.  All disjoint
 // column pairs of a round-robin round are processed at once, each by a group
@@ -430,84 +488,133 @@ __device__ void jacobi_svd_lds(double* A, double* V, int n, double thr2, double*
   }
 }
 
-// Single-wave variant for n <= 64: the whole round-robin round is done by
-// the first wave (g = 64 / pairs lanes per pair, rounded down to a power of
-// two) with wave-scope ordering of the LDS traffic instead of work-group
-// barriers between rounds; the other waves only join at the end.
+// Rotation of a Jacobi pair from al = |x|^2, be = |y|^2, ga = x.y: the
+// tangent is the smaller root of t^2 + 2 zeta t - 1 = 0, zeta = (be - al) /
+// (2 ga), written without the division by ga.  Hardware reciprocal and
+// reciprocal square root with one Newton step each: c^2 + s^2 = 1 to a few
+// ulp, which is all a rotation needs (the angle itself may be inexact).
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  return y * fma(-x, y, 2.0);
+}
+__device__ __forceinline__ void jacobi_rotation(double al, double be, double ga, double& cs, double& sn) {
+  const double d = be - al;
+  const double q = fma(d, d, 4.0 * ga * ga);
+  const double h = q * rsq_nr(q);
+  const double tt = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) * rcp_nr(fabs(d) + h);
+  cs = rsq_nr(fma(tt, tt, 1.0));
+  sn = cs * tt;
+}
+
+// Single-wave one-sided Jacobi for n <= 64, run by the first wave only
+// (V accumulated; V must hold the identity or a start basis): every
+// round-robin round is done by that wave (g = 64 / pairs lanes per pair,
+// rounded down to a power of two), each lane keeping its rows of the pair in
+// registers, with wave-scope ordering of the LDS traffic between rounds
+// instead of work-group barriers.
+__device__ void jacobi_wave_core(double* A, double* V, int n, double thr2) {
+  const int tid = threadIdx.x;
+  const int np = (n + 1) & ~1;
+  const int npairs = np / 2;
+  int g = 64;
+  while (g > 1 && npairs * g > 64) g >>= 1;
+  const int grp = tid / g, gl = tid % g;
+  const double tol = fmax(1e-14, 8.0 * 2.220446049250313e-16 * n);
+  const double tol2 = tol * tol;
+  constexpr int RU = 16;
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    double off2 = 0.0;
+    for (int rnd = 0; rnd < np - 1; ++rnd) {
+      if (grp < npairs) {
+        int a, b;
+        if (grp == 0) {
+          a = np - 1;
+          b = rnd;
+        } else {
+          a = (rnd + grp) % (np - 1);
+          b = (rnd - grp + (np - 1)) % (np - 1);
+        }
+        if (a < n && b < n) {
+          const int pp = min(a, b), qq = max(a, b);
+          double* __restrict__ Ap = A + pp * SM;
+          double* __restrict__ Aq = A + qq * SM;
+          double xr[RU], yr[RU];
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            const int i = gl + g * u;
+            xr[u] = i < n ? Ap[i] : 0.0;
+            yr[u] = i < n ? Aq[i] : 0.0;
+          }
+          double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            al = fma(xr[u], xr[u], al);
+            be = fma(yr[u], yr[u], be);
+            ga = fma(xr[u], yr[u], ga);
+          }
+          for (int i = gl + g * RU; i < n; i += g) {
+            const double x = Ap[i], y = Aq[i];
+            al = fma(x, x, al);
+            be = fma(y, y, be);
+            ga = fma(x, y, ga);
+          }
+          for (int o = g >> 1; o > 0; o >>= 1) {
+            al += __shfl_xor(al, o);
+            be += __shfl_xor(be, o);
+            ga += __shfl_xor(ga, o);
+          }
+          if (ga != 0.0 && al != 0.0 && be != 0.0 && (al >= thr2 || be >= thr2)) {
+            const double g2 = ga * ga, ab = al * be;
+            off2 = fmax(off2, g2 / ab);
+            if (g2 >= tol2 * ab) {
+              double cs, sn;
+              jacobi_rotation(al, be, ga, cs, sn);
+              double* __restrict__ Vp = V + pp * SM;
+              double* __restrict__ Vq = V + qq * SM;
+#pragma unroll
+              for (int u = 0; u < RU; ++u) {
+                const int i = gl + g * u;
+                if (i < n) {
+                  Ap[i] = cs * xr[u] - sn * yr[u];
+                  Aq[i] = sn * xr[u] + cs * yr[u];
+                }
+              }
+              for (int i = gl + g * RU; i < n; i += g) {
+                const double x = Ap[i], y = Aq[i];
+                Ap[i] = cs * x - sn * y;
+                Aq[i] = sn * x + cs * y;
+              }
+#pragma unroll 4
+              for (int i = gl; i < n; i += g) {
+                const double v1 = Vp[i], v2 = Vq[i];
+                Vp[i] = cs * v1 - sn * v2;
+                Vq[i] = sn * v1 + cs * v2;
+              }
+            }
+          }
+        }
+      }
+      wave_sync_lds();
+    }
+    for (int o = 32; o > 0; o >>= 1) off2 = fmax(off2, __shfl_xor(off2, o));
+    if (off2 < tol2) break;
+  }
+}
+
+// Work-group entry of the single-wave Jacobi (V := identity first).
 __device__ void jacobi_svd_wave(double* A, double* V, int n, double thr2, double* red) {
+  (void)red;
   const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += 256) {
     int i = e % n, j = e / n;
     V[i + j * SM] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (tid < 64) {
-    const int np = (n + 1) & ~1;
-    const int npairs = np / 2;
-    int g = 64;
-    while (g > 1 && npairs * g > 64) g >>= 1;
-    const int grp = tid / g, gl = tid % g;
-    const double tol = fmax(1e-14, 8.0 * 2.220446049250313e-16 * n);
-    const double tol2 = tol * tol;
-    for (int sweep = 0; sweep < 30; ++sweep) {
-      double off2 = 0.0;
-      for (int rnd = 0; rnd < np - 1; ++rnd) {
-        if (grp < npairs) {
-          int a, b;
-          if (grp == 0) {
-            a = np - 1;
-            b = rnd;
-          } else {
-            a = (rnd + grp) % (np - 1);
-            b = (rnd - grp + (np - 1)) % (np - 1);
-          }
-          if (a < n && b < n) {
-            const int pp = min(a, b), qq = max(a, b);
-            double* __restrict__ Ap = A + pp * SM;
-            double* __restrict__ Aq = A + qq * SM;
-            double al = 0.0, be = 0.0, ga = 0.0;
-            for (int i = gl; i < n; i += g) {
-              const double x = Ap[i], y = Aq[i];
-              al = fma(x, x, al);
-              be = fma(y, y, be);
-              ga = fma(x, y, ga);
-            }
-            for (int o = g >> 1; o > 0; o >>= 1) {
-              al += __shfl_xor(al, o);
-              be += __shfl_xor(be, o);
-              ga += __shfl_xor(ga, o);
-            }
-            if (ga != 0.0 && al != 0.0 && be != 0.0 && (al >= thr2 || be >= thr2)) {
-              const double g2 = ga * ga, ab = al * be;
-              off2 = fmax(off2, g2 / ab);
-              if (g2 >= tol2 * ab) {
-                const double d = be - al;
-                const double h = sqrt(fma(d, d, 4.0 * g2));
-                const double tt = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + h);
-                const double cs = 1.0 / sqrt(fma(tt, tt, 1.0));
-                const double sn = cs * tt;
-                double* __restrict__ Vp = V + pp * SM;
-                double* __restrict__ Vq = V + qq * SM;
-                for (int i = gl; i < n; i += g) {
-                  const double x = Ap[i], y = Aq[i], vx = Vp[i], vy = Vq[i];
-                  Ap[i] = cs * x - sn * y;
-                  Aq[i] = sn * x + cs * y;
-                  Vp[i] = cs * vx - sn * vy;
-                  Vq[i] = sn * vx + cs * vy;
-                }
-              }
-            }
-          }
-        }
-        // the next round reads columns written by other lanes of this wave
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      }
-      for (int o = 32; o > 0; o >>= 1) off2 = fmax(off2, __shfl_xor(off2, o));
-      if (off2 < tol2) break;
-    }
-  }
+  if (tid < 64) jacobi_wave_core(A, V, n, thr2);
   __syncthreads();
 }
 
@@ -680,6 +787,79 @@ __device__ int qrcp_lds(double* A, int n, double tau, double* cn, double* cn0, i
   return k;
 }
 
+// Single-wave column-pivoted QR for n <= 64 (lanes = columns).  The matrix
+// is kept transposed in LDS (row i at T[i * TLD], lane l owns column l), so
+// a lane's accesses are conflict-free and the pivot column is read by every
+// lane as a broadcast; steps are ordered by wave-scope fences, not barriers.
+// Same contract as qrcp_lds: returns k, with R' in pivot order
+// (R'[r][c] = T[r * TLD + piv[c]]) and piv[0..n) a permutation whose first
+// k entries are the chosen columns.
+constexpr int TLD = 65;
+
+__device__ int qrcp_wave(double* T, int n, double tau, int* piv, int* kout) {
+  const int lane = threadIdx.x;   // called by the first wave only
+  bool active = lane < n;
+  double cn = 0.0;
+  if (active)
+    for (int i = 0; i < n; ++i) cn = fma(T[i * TLD + lane], T[i * TLD + lane], cn);
+  double cn0 = cn;
+  double r0 = 0.0;
+  int k = n;
+  for (int j = 0; j < n; ++j) {
+    // pivot: the largest remaining norm, ties to the lowest column
+    double bv = active ? cn : -1.0;
+    int bi = lane;
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(bv, o);
+      const int oi = __shfl_xor(bi, o);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
+      }
+    }
+    const int p = bi;
+    // exact norm of the pivot column below row j (broadcast reads)
+    double sq = 0.0;
+    for (int i = j; i < n; ++i) sq = fma(T[i * TLD + p], T[i * TLD + p], sq);
+    const double nrm = sqrt(sq);
+    if (j == 0) r0 = nrm;
+    if (!(nrm > tau * r0) || !(nrm > 0.0)) {
+      k = j;
+      break;
+    }
+    const double a = T[j * TLD + p];
+    const double alpha = (a >= 0.0) ? -nrm : nrm;
+    const double beta = 2.0 / (2.0 * nrm * (nrm + fabs(a)));
+    const double vj = a - alpha;
+    if (lane == p) active = false;
+    if (active) {
+      double w = vj * T[j * TLD + lane];
+      for (int i = j + 1; i < n; ++i) w = fma(T[i * TLD + p], T[i * TLD + lane], w);
+      w *= beta;
+      T[j * TLD + lane] -= w * vj;
+      for (int i = j + 1; i < n; ++i) T[i * TLD + lane] -= w * T[i * TLD + p];
+      const double r = T[j * TLD + lane];
+      double c = cn - r * r;
+      if (!(c > 1e-8 * cn0)) {
+        c = 0.0;
+        for (int i = j + 1; i < n; ++i) c = fma(T[i * TLD + lane], T[i * TLD + lane], c);
+        cn0 = c;
+      }
+      cn = c;
+    }
+    if (lane == p) T[j * TLD + p] = alpha;
+    if (lane == 0) piv[j] = p;
+    wave_sync_lds();
+  }
+  // the columns never chosen follow in increasing order, so that piv[0..n)
+  // is a permutation (their rows of the result are zero)
+  const unsigned long long rest = __ballot(active);
+  if (active) piv[k + __popcll(rest & ((1ull << lane) - 1ull))] = lane;
+  if (lane == 0) *kout = k;
+  wave_sync_lds();
+  return k;
+}
+
 // Householder QR of the n x n matrix M in LDS (ld SM) that keeps the
 // reflectors: on exit R is in the upper triangle, v_j below the diagonal of
 // column j with its leading entry in vtop[j], and H_j = I - beta[j] v_j v_j^T,
@@ -753,6 +933,37 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
   load_upper(refp(bufs, J.R1), rmax, n, R1);
   if (J.kind != SK_SKETCH_P) load_upper(refp(bufs, J.R2), rmax, n, R2);
   __syncthreads();
+  if (J.kind == SK_SKETCH_P && n <= 64) {
+    // single-wave pivoted QR on R1 transposed into V (row i at V[i * TLD])
+    __shared__ int s_k;
+    for (int e = tid; e < n * n; e += 256) {
+      int i = e / n, l = e % n;
+      V[i * TLD + l] = (i <= l) ? R1[upk(i, l)] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) qrcp_wave(V, n, eps, ord, &s_k);
+    __syncthreads();
+    const int kk = s_k;
+    // X = R'_k^{-1} (R'[r][c] = V[r * TLD + ord[c]]), thread c builds column c
+    // in A (row i at A[i * TLD]) from e_c by column-oriented back substitution
+    for (int c = tid; c < kk; c += 256) {
+      for (int i = 0; i <= c; ++i) A[i * TLD + c] = (i == c) ? 1.0 : 0.0;
+      for (int l = c; l >= 0; --l) {
+        const int pl = ord[l];
+        const double xl = A[l * TLD + c] / V[l * TLD + pl];
+        A[l * TLD + c] = xl;
+        for (int i = 0; i < l; ++i) A[i * TLD + c] -= V[i * TLD + pl] * xl;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * kk; e += 256) {
+      int i = e % n, c = e / n;
+      double v = (i <= c && i < kk) ? A[i * TLD + c] : 0.0;
+      C1[ord[i] + (size_t)c * rmax] = v;
+    }
+    if (tid == 0) dyn[J.out_rank_slot] = kk;
+    return;
+  }
   if (J.kind == SK_SKETCH_P) {
     for (int e = tid; e < n * n; e += 256) {
       int i = e % n, j = e / n;
@@ -778,6 +989,133 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
       C1[ord[i] + (size_t)c * rmax] = v;
     }
     if (tid == 0) dyn[J.out_rank_slot] = kk;
+    return;
+  }
+  if (J.kind == SK_SKETCH_F && n <= 64) {
+    // The whole truncation by the first wave (lanes = rows of M = columns of
+    // M^T), phases ordered by wave-scope fences:
+    //   M = R1 R2^{-1};  M^T = Q2 R2' (Householder, reflectors kept);
+    //   one-sided Jacobi on B = R2'^T with V;  Z = Q2 V[:, ord];
+    //   C1 = R2^{-1} Z_k.
+    __shared__ int s_kk;
+    if (tid < 64) {
+      const int lane = tid;
+      // M column by column (col-major in A); a lane reads only its own row
+      for (int j = 0; j < n; ++j) {
+        if (lane < n) {
+          double acc = (lane <= j) ? R1[upk(lane, j)] : 0.0;
+          for (int l = 0; l < j; ++l) acc = fma(-A[lane + l * SM], R2[upk(l, j)], acc);
+          const double d = R2[upk(j, j)];
+          A[lane + j * SM] = (d != 0.0) ? acc / d : 0.0;
+        }
+      }
+      wave_sync_lds();
+      // Householder QR of T = M^T: T[i][l] = A[l + i * SM], lane l owns column l
+      for (int j = 0; j < n; ++j) {
+        double sq = 0.0;
+        for (int i = j; i < n; ++i) sq = fma(A[j + i * SM], A[j + i * SM], sq);
+        const double nrm = sqrt(sq);
+        const double a = A[j + j * SM];
+        const double alpha = (a >= 0.0) ? -nrm : nrm;
+        const double vtv = 2.0 * nrm * (nrm + fabs(a));
+        const double bj = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+        const double vj = a - alpha;
+        if (lane > j && lane < n && bj != 0.0) {
+          double w = vj * A[lane + j * SM];
+          for (int i = j + 1; i < n; ++i) w = fma(A[j + i * SM], A[lane + i * SM], w);
+          w *= bj;
+          A[lane + j * SM] -= w * vj;
+          for (int i = j + 1; i < n; ++i) A[lane + i * SM] -= w * A[j + i * SM];
+        }
+        if (lane == j) {
+          A[j + j * SM] = alpha;
+          beta[j] = bj;
+          beta[SM + j] = vj;
+        }
+        wave_sync_lds();
+      }
+      // reflector j (rows i > j of T's column j = A[j + i * SM], the strict
+      // upper triangle of A) to R1's packed storage; A keeps B = R2'^T
+      for (int j = 0; j < n; ++j) {
+        const int i = lane;
+        if (i > j && i < n) {
+          R1[j * n - j * (j + 1) / 2 + (i - j - 1)] = A[j + i * SM];
+          A[j + i * SM] = 0.0;
+        }
+      }
+      wave_sync_lds();   // rows of A read below were zeroed by other lanes
+      for (int e = lane; e < n * n; e += 64) {
+        const int i = e % n, j = e / n;
+        V[i + j * SM] = (i == j) ? 1.0 : 0.0;
+      }
+      double f2 = 0.0;
+      if (lane < n)
+        for (int c = 0; c < n; ++c) f2 = fma(A[lane + c * SM], A[lane + c * SM], f2);
+      for (int o = 32; o > 0; o >>= 1) f2 += __shfl_xor(f2, o);
+      wave_sync_lds();
+      const double dt = 1e-3 * eps;
+      jacobi_wave_core(A, V, n, dt * dt * f2);
+      // singular values and their order (ties to the lower index)
+      if (lane < n) {
+        double q = 0.0;
+        for (int i = 0; i < n; ++i) q = fma(A[i + lane * SM], A[i + lane * SM], q);
+        sv[lane] = sqrt(q);
+      }
+      wave_sync_lds();
+      if (lane < n) {
+        // a NaN sorts last, so that ord is a permutation whatever sv holds
+        const double me = sv[lane] == sv[lane] ? sv[lane] : -1.0;
+        int r = 0;
+        for (int i = 0; i < n; ++i) {
+          const double o = sv[i] == sv[i] ? sv[i] : -1.0;
+          r += (o > me) || (o == me && i < lane);
+        }
+        ord[r] = lane;
+      }
+      wave_sync_lds();
+      const double smax = sv[ord[0]];
+      int kk = 0;
+      if (smax > 0.0 && isfinite(smax)) {
+        while (kk < n && sv[ord[kk]] > eps * smax) ++kk;
+      } else if (!isfinite(smax) && lane == 0) {
+        atomicOr(status, STAT_NONFINITE);
+      }
+      if (kk > J.cap) {
+        if (lane == 0) atomicOr(status, STAT_RANK_OVERFLOW);
+        kk = J.cap;
+      }
+      if (J.sat.maxv >= 0 && kk >= dimv(dyn, J.sat) && lane == 0) atomicOr(status, STAT_SKETCH_SAT);
+      // Z = Q2 V[:, ord[c]] (lane c, row i at A[i * TLD + c]); A is free now
+      const int c = lane;
+      if (c < kk)
+        for (int i = 0; i < n; ++i) A[i * TLD + c] = V[i + ord[c] * SM];
+      for (int j = n - 1; j >= 0; --j) {
+        const double bj = beta[j];
+        if (c < kk && bj != 0.0) {
+          const double* vj = R1 + j * n - j * (j + 1) / 2;
+          const double v0 = beta[SM + j];
+          double d = v0 * A[j * TLD + c];
+          for (int i = j + 1; i < n; ++i) d = fma(vj[i - j - 1], A[i * TLD + c], d);
+          d *= bj;
+          A[j * TLD + c] -= d * v0;
+          for (int i = j + 1; i < n; ++i) A[i * TLD + c] -= d * vj[i - j - 1];
+        }
+      }
+      // C1 = R2^{-1} Z_k by back substitution in place
+      if (c < kk) {
+        for (int i = n - 1; i >= 0; --i) {
+          double acc = A[i * TLD + c];
+          for (int l = i + 1; l < n; ++l) acc = fma(-R2[upk(i, l)], A[l * TLD + c], acc);
+          const double d = R2[upk(i, i)];
+          const double x = (d != 0.0) ? acc / d : 0.0;
+          A[i * TLD + c] = x;
+          C1[i + (size_t)c * rmax] = x;
+        }
+      }
+      if (lane == 0) s_kk = kk;
+    }
+    __syncthreads();
+    if (tid == 0) dyn[J.out_rank_slot] = s_kk;
     return;
   }
   // ---- form the matrix to decompose
