@@ -510,87 +510,97 @@ __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga,
   sn = cs * tt;
 }
 
+// Cross-lane moves inside a row of 16 lanes (DPP: a plain vector
+// instruction, no LDS round trip), applied to both halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8
+constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15 - i within 16
+
+// Sum over an aligned group of G lanes; every lane of the group gets the
+// same bits (each level adds a lane's value to its partner's, and the
+// partner computes the same two operands in the other order).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (G >= 64) v += __shfl_xor(v, 32);
+  if constexpr (G >= 32) v += __shfl_xor(v, 16);
+  if constexpr (G >= 16) v += dpp_move<DPP_MIRROR>(v);
+  if constexpr (G >= 8) v += dpp_move<DPP_HALF_MIRROR>(v);
+  if constexpr (G >= 4) v += dpp_move<DPP_XOR2>(v);
+  if constexpr (G >= 2) v += dpp_move<DPP_XOR1>(v);
+  return v;
+}
+
 // Single-wave one-sided Jacobi for n <= 64, run by the first wave only
-// (V accumulated; V must hold the identity or a start basis): every
-// round-robin round is done by that wave (g = 64 / pairs lanes per pair,
-// rounded down to a power of two), each lane keeping its rows of the pair in
-// registers, with wave-scope ordering of the LDS traffic between rounds
-// instead of work-group barriers.
-__device__ void jacobi_wave_core(double* A, double* V, int n, double thr2) {
+// (V accumulated; V must hold the identity or a start basis).  Every
+// round-robin round is done by that wave: G lanes per column pair (G a
+// power of two with pairs * G <= 64), each lane holding RU >= n / G rows of
+// both columns of A and of V in registers for the round, with wave-scope
+// ordering of the LDS traffic between rounds instead of work-group barriers.
+template <int G, int RU, bool VREG>
+__device__ void jacobi_wave_rounds(double* A, double* V, int n, double thr2) {
   const int tid = threadIdx.x;
   const int np = (n + 1) & ~1;
   const int npairs = np / 2;
-  int g = 64;
-  while (g > 1 && npairs * g > 64) g >>= 1;
-  const int grp = tid / g, gl = tid % g;
+  const int grp = tid / G, gl = tid % G;
   const double tol = fmax(1e-14, 8.0 * 2.220446049250313e-16 * n);
   const double tol2 = tol * tol;
-  constexpr int RU = 16;
   for (int sweep = 0; sweep < 30; ++sweep) {
     double off2 = 0.0;
     for (int rnd = 0; rnd < np - 1; ++rnd) {
-      if (grp < npairs) {
-        int a, b;
-        if (grp == 0) {
-          a = np - 1;
-          b = rnd;
-        } else {
-          a = (rnd + grp) % (np - 1);
-          b = (rnd - grp + (np - 1)) % (np - 1);
+      int a = np - 1, b = rnd;
+      if (grp > 0) {
+        a = (rnd + grp) % (np - 1);
+        b = (rnd - grp + (np - 1)) % (np - 1);
+      }
+      if (grp < npairs && a < n && b < n) {
+        const int pp = min(a, b), qq = max(a, b);
+        double* __restrict__ Ap = A + pp * SM;
+        double* __restrict__ Aq = A + qq * SM;
+        double* __restrict__ Vp = V + pp * SM;
+        double* __restrict__ Vq = V + qq * SM;
+        double xr[RU], yr[RU], vx[VREG ? RU : 1], vy[VREG ? RU : 1];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          const int i = gl + G * u;
+          const bool in = i < n;
+          xr[u] = in ? Ap[i] : 0.0;
+          yr[u] = in ? Aq[i] : 0.0;
+          if (VREG) {
+            vx[u] = in ? Vp[i] : 0.0;
+            vy[u] = in ? Vq[i] : 0.0;
+          }
         }
-        if (a < n && b < n) {
-          const int pp = min(a, b), qq = max(a, b);
-          double* __restrict__ Ap = A + pp * SM;
-          double* __restrict__ Aq = A + qq * SM;
-          double xr[RU], yr[RU];
+        double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-          for (int u = 0; u < RU; ++u) {
-            const int i = gl + g * u;
-            xr[u] = i < n ? Ap[i] : 0.0;
-            yr[u] = i < n ? Aq[i] : 0.0;
-          }
-          double al = 0.0, be = 0.0, ga = 0.0;
+        for (int u = 0; u < RU; ++u) {
+          al = fma(xr[u], xr[u], al);
+          be = fma(yr[u], yr[u], be);
+          ga = fma(xr[u], yr[u], ga);
+        }
+        al = group_sum<G>(al);
+        be = group_sum<G>(be);
+        ga = group_sum<G>(ga);
+        if (ga != 0.0 && al != 0.0 && be != 0.0 && (al >= thr2 || be >= thr2)) {
+          const double g2 = ga * ga, ab = al * be;
+          off2 = fmax(off2, g2 / ab);
+          if (g2 >= tol2 * ab) {
+            double cs, sn;
+            jacobi_rotation(al, be, ga, cs, sn);
 #pragma unroll
-          for (int u = 0; u < RU; ++u) {
-            al = fma(xr[u], xr[u], al);
-            be = fma(yr[u], yr[u], be);
-            ga = fma(xr[u], yr[u], ga);
-          }
-          for (int i = gl + g * RU; i < n; i += g) {
-            const double x = Ap[i], y = Aq[i];
-            al = fma(x, x, al);
-            be = fma(y, y, be);
-            ga = fma(x, y, ga);
-          }
-          for (int o = g >> 1; o > 0; o >>= 1) {
-            al += __shfl_xor(al, o);
-            be += __shfl_xor(be, o);
-            ga += __shfl_xor(ga, o);
-          }
-          if (ga != 0.0 && al != 0.0 && be != 0.0 && (al >= thr2 || be >= thr2)) {
-            const double g2 = ga * ga, ab = al * be;
-            off2 = fmax(off2, g2 / ab);
-            if (g2 >= tol2 * ab) {
-              double cs, sn;
-              jacobi_rotation(al, be, ga, cs, sn);
-              double* __restrict__ Vp = V + pp * SM;
-              double* __restrict__ Vq = V + qq * SM;
-#pragma unroll
-              for (int u = 0; u < RU; ++u) {
-                const int i = gl + g * u;
-                if (i < n) {
-                  Ap[i] = cs * xr[u] - sn * yr[u];
-                  Aq[i] = sn * xr[u] + cs * yr[u];
-                }
-              }
-              for (int i = gl + g * RU; i < n; i += g) {
-                const double x = Ap[i], y = Aq[i];
-                Ap[i] = cs * x - sn * y;
-                Aq[i] = sn * x + cs * y;
-              }
-#pragma unroll 4
-              for (int i = gl; i < n; i += g) {
-                const double v1 = Vp[i], v2 = Vq[i];
+            for (int u = 0; u < RU; ++u) {
+              const int i = gl + G * u;
+              if (i < n) {
+                Ap[i] = cs * xr[u] - sn * yr[u];
+                Aq[i] = sn * xr[u] + cs * yr[u];
+                const double v1 = VREG ? vx[u] : Vp[i], v2 = VREG ? vy[u] : Vq[i];
                 Vp[i] = cs * v1 - sn * v2;
                 Vq[i] = sn * v1 + cs * v2;
               }
@@ -603,6 +613,25 @@ __device__ void jacobi_wave_core(double* A, double* V, int n, double thr2) {
     for (int o = 32; o > 0; o >>= 1) off2 = fmax(off2, __shfl_xor(off2, o));
     if (off2 < tol2) break;
   }
+}
+
+__device__ void jacobi_wave_core(double* A, double* V, int n, double thr2) {
+  // pairs * G <= 64 and RU * G >= n for each size class
+  // (V stays in LDS for the two largest classes to bound the register count)
+  if (n <= 2)
+    jacobi_wave_rounds<64, 1, true>(A, V, n, thr2);
+  else if (n <= 4)
+    jacobi_wave_rounds<32, 1, true>(A, V, n, thr2);
+  else if (n <= 8)
+    jacobi_wave_rounds<16, 1, true>(A, V, n, thr2);
+  else if (n <= 16)
+    jacobi_wave_rounds<8, 2, true>(A, V, n, thr2);
+  else if (n <= 32)
+    jacobi_wave_rounds<4, 8, true>(A, V, n, thr2);
+  else if (n <= 48)
+    jacobi_wave_rounds<2, 24, false>(A, V, n, thr2);
+  else
+    jacobi_wave_rounds<2, 32, false>(A, V, n, thr2);
 }
 
 // Work-group entry of the single-wave Jacobi (V := identity first).
