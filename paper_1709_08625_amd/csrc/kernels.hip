@@ -48,18 +48,17 @@ struct ProdMeta {
   int live;
 };
 
-template <class T, int NX, int NY>
-__device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const int* __restrict__ dyn, const GemmJob& J,
-                                          const GemmProd* __restrict__ prods, int m, int n, int r0,
-                                          int c0, T (*As)[GT + 1], T (*Bs)[GT + 1], ProdMeta* pm) {
+// The product pipeline of a tile, shared by the vector and matrix-core
+// bodies: products are taken in batches of PBATCH descriptors; element-wise
+// additions (tb == 2) go to on_add(M); every other live product streams its
+// k range through LDS in chunks of GK, the next (product, chunk) pair's
+// global loads in flight while on_chunk(kl) consumes the current chunk.
+template <class T, class AddF, class ChunkF>
+__device__ __forceinline__ void gemm_products(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
+                                              const GemmJob& J, const GemmProd* __restrict__ prods, int m,
+                                              int n, int r0, int c0, T (*As)[GT + 1], T (*Bs)[GT + 1],
+                                              ProdMeta* pm, AddF on_add, ChunkF on_chunk) {
   const int tid = threadIdx.x;
-  const int ty = tid & 15, tx = tid >> 4;   // rows follow the lane index (coalesced C and tb==2 access)
-  T acc[NX][NY];
-#pragma unroll
-  for (int a = 0; a < NX; ++a)
-#pragma unroll
-    for (int b = 0; b < NY; ++b) acc[a][b] = T(0);
-
   // element e of a chunk: A chunk is GT x GK, B chunk GK x GT; the index
   // split follows the operand's storage order so that lanes coalesce
   T ra[GR], rb[GR];
@@ -131,18 +130,9 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
     // element-wise additions of partial sums (tb == 2)
     for (int q = 0; q < cnt; ++q) {
       const ProdMeta& M = pmc[q];
-      if (!M.live || M.tb != 2) continue;
-#pragma unroll
-      for (int x = 0; x < NX; ++x)
-#pragma unroll
-        for (int y = 0; y < NY; ++y) {
-          int gi = r0 + ty + 16 * x, gj = c0 + tx + 16 * y;
-          if (gi >= M.pr0 && gi < M.pr1 && gj >= M.pc0 && gj < M.pc1)
-            acc[x][y] += T(M.alpha * M.A[(gi - M.pr0) + (size_t)(gj - M.pc0) * M.lda]);
-        }
+      if (M.live && M.tb == 2) on_add(M);
     }
-    // products: (product, k-chunk) pairs in order, the next pair's global
-    // loads in flight while the current one is consumed from LDS
+    // products: (product, k-chunk) pairs in order
     auto next_live = [&](int q) {
       while (q < cnt && (!pmc[q].live || pmc[q].tb == 2)) ++q;
       return q;
@@ -161,23 +151,51 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
         nk0 = 0;
       }
       if (nq < cnt) fetch(pmc[nq], nk0);
-      const int kl = min(GK, pmc[q].k - k0);
-#pragma unroll 8
-      for (int kk = 0; kk < kl; ++kk) {
-        T av[NX], bv[NY];
-#pragma unroll
-        for (int z = 0; z < NX; ++z) av[z] = As[kk][ty + 16 * z];
-#pragma unroll
-        for (int z = 0; z < NY; ++z) bv[z] = Bs[kk][tx + 16 * z];
-#pragma unroll
-        for (int x = 0; x < NX; ++x)
-#pragma unroll
-          for (int y = 0; y < NY; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
-      }
+      on_chunk(min(GK, pmc[q].k - k0));
       q = nq;
       k0 = nk0;
     }
   }
+}
+
+// Vector body: thread (ty, tx) accumulates rows ty + 16 x and columns
+// tx + 16 y of the tile (FP32 in mixed precision).
+template <class T, int NX, int NY>
+__device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const int* __restrict__ dyn, const GemmJob& J,
+                                          const GemmProd* __restrict__ prods, int m, int n, int r0,
+                                          int c0, T (*As)[GT + 1], T (*Bs)[GT + 1], ProdMeta* pm) {
+  const int tid = threadIdx.x;
+  const int ty = tid & 15, tx = tid >> 4;   // rows follow the lane index (coalesced C and tb==2 access)
+  T acc[NX][NY];
+#pragma unroll
+  for (int a = 0; a < NX; ++a)
+#pragma unroll
+    for (int b = 0; b < NY; ++b) acc[a][b] = T(0);
+  auto on_add = [&](const ProdMeta& M) {
+#pragma unroll
+    for (int x = 0; x < NX; ++x)
+#pragma unroll
+      for (int y = 0; y < NY; ++y) {
+        int gi = r0 + ty + 16 * x, gj = c0 + tx + 16 * y;
+        if (gi >= M.pr0 && gi < M.pr1 && gj >= M.pc0 && gj < M.pc1)
+          acc[x][y] += T(M.alpha * M.A[(gi - M.pr0) + (size_t)(gj - M.pc0) * M.lda]);
+      }
+  };
+  auto on_chunk = [&](int kl) {
+#pragma unroll 8
+    for (int kk = 0; kk < kl; ++kk) {
+      T av[NX], bv[NY];
+#pragma unroll
+      for (int z = 0; z < NX; ++z) av[z] = As[kk][ty + 16 * z];
+#pragma unroll
+      for (int z = 0; z < NY; ++z) bv[z] = Bs[kk][tx + 16 * z];
+#pragma unroll
+      for (int x = 0; x < NX; ++x)
+#pragma unroll
+        for (int y = 0; y < NY; ++y) acc[x][y] = fma(av[x], bv[y], acc[x][y]);
+    }
+  };
+  gemm_products<T>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm, on_add, on_chunk);
   double* __restrict__ C = refp(bufs, J.C);
   const int ldc = J.C.ld;
 #pragma unroll
@@ -190,6 +208,110 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
       if (gj >= n) continue;
       size_t o = gi + (size_t)gj * ldc;
       C[o] = J.zero ? double(acc[x][y]) : C[o] + double(acc[x][y]);
+    }
+  }
+}
+
+// Matrix-core body (FP64): the live 16 x 16 blocks of the tile are spread
+// over the four waves; with fewer than four blocks the waves of a block
+// split its k steps and their partial sums are added in wave order at the
+// end (deterministic).  Each step is one FP64 16x16x4 matrix instruction
+// computing the transposed block, D' = B^T A^T, so that lane L holds the
+// element (row L % 16, column 4 r + L / 16) of the block in its register r:
+// sixteen consecutive rows of a column, a coalesced store.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
+                                               const GemmJob& J, const GemmProd* __restrict__ prods, int m,
+                                               int n, int r0, int c0, double (*As)[GT + 1], double (*Bs)[GT + 1],
+                                               ProdMeta* pm) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int er = min(GT, m - r0), ec = min(GT, n - c0);
+  const int nbr = (er + 15) >> 4, nbc = (ec + 15) >> 4, nblk = nbr * nbc;
+  const int nsplit = nblk == 1 ? 4 : (nblk == 2 ? 2 : 1);
+  int kpart = 0, nb = 0;
+  int bi[4] = {0, 0, 0, 0}, bj[4] = {0, 0, 0, 0};
+  if (nsplit > 1) {
+    const int b = wave / nsplit;
+    kpart = wave % nsplit;
+    nb = 1;
+    bi[0] = b % nbr;
+    bj[0] = b / nbr;
+  } else {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int b = wave + 4 * t;
+      if (b < nblk) {
+        bi[t] = b % nbr;
+        bj[t] = b / nbr;
+        nb = t + 1;
+      }
+    }
+  }
+  dbl4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = dbl4{0.0, 0.0, 0.0, 0.0};
+  auto on_add = [&](const ProdMeta& M) {
+    if (kpart != 0) return;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < nb) {
+        const int gi = r0 + 16 * bi[t] + li;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int gj = c0 + 16 * bj[t] + 4 * r + lk;
+          if (gi >= M.pr0 && gi < M.pr1 && gj >= M.pc0 && gj < M.pc1)
+            acc[t][r] += M.alpha * M.A[(gi - M.pr0) + (size_t)(gj - M.pc0) * M.lda];
+        }
+      }
+    }
+  };
+  auto on_chunk = [&](int kl) {
+    const int ns = (kl + 3) >> 2;
+    for (int s = kpart; s < ns; s += nsplit) {
+      const int kr = 4 * s + lk;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (t < nb) {
+          const double av = Bs[kr][16 * bj[t] + li];
+          const double bv = As[kr][16 * bi[t] + li];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+        }
+      }
+    }
+  };
+  gemm_products<double>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm, on_add, on_chunk);
+  if (nsplit > 1) {
+    // partial sums of the k split: waves with kpart > 0 hand theirs over
+    double* red = &As[0][0];
+    __syncthreads();
+    if (kpart > 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[(wave * 4 + r) * 64 + lane] = acc[0][r];
+    }
+    __syncthreads();
+    if (kpart == 0) {
+      for (int w = 1; w < nsplit; ++w) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[0][r] += red[((wave + w) * 4 + r) * 64 + lane];
+      }
+    }
+  }
+  if (kpart != 0) return;
+  double* __restrict__ C = refp(bufs, J.C);
+  const int ldc = J.C.ld;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t < nb) {
+      const int gi = r0 + 16 * bi[t] + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gj = c0 + 16 * bj[t] + 4 * r + lk;
+        if (gi < m && gj < n) {
+          const size_t o = gi + (size_t)gj * ldc;
+          C[o] = J.zero ? acc[t][r] : C[o] + acc[t][r];
+        }
+      }
     }
   }
 }
@@ -225,17 +347,7 @@ __global__ __launch_bounds__(256) void k_gemm(const Bufs* __restrict__ bufs, con
     }
     return;
   }
-  switch (nx * 8 + ny) {
-    case 9: gemm_tile<double, 1, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
-    case 10: gemm_tile<double, 1, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
-    case 12: gemm_tile<double, 1, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
-    case 17: gemm_tile<double, 2, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
-    case 18: gemm_tile<double, 2, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
-    case 20: gemm_tile<double, 2, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
-    case 33: gemm_tile<double, 4, 1>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
-    case 34: gemm_tile<double, 4, 2>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
-    default: gemm_tile<double, 4, 4>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm); break;
-  }
+  gemm_tile_mfma(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm);
 }
 
 // ------------------------------------------------------------------ TSQR
@@ -538,45 +650,39 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-// Single-wave one-sided Jacobi for n <= 64, run by the first wave only
-// (V accumulated; V must hold the identity or a start basis).  Every
-// round-robin round is done by that wave: G lanes per column pair (G a
-// power of two with pairs * G <= 64), each lane holding RU >= n / G rows of
-// both columns of A and of V in registers for the round, with wave-scope
-// ordering of the LDS traffic between rounds instead of work-group barriers.
-template <int G, int RU, bool VREG>
-__device__ void jacobi_wave_rounds(double* A, double* V, int n, double thr2) {
+// Work-group one-sided Jacobi for n <= 64 (all 256 threads; V accumulated,
+// V must hold the identity or a start basis): G lanes per column pair
+// (pairs * G <= 256, G <= 16 so that a group lies in one row of 16 lanes and
+// reduces with DPP), RU >= n / G rows of both columns of A and V per lane
+// in registers for the round, one barrier per round.
+template <int G, int RU>
+__device__ void jacobi_wg_rounds(double* A, double* V, int n, double thr2) {
   const int tid = threadIdx.x;
   const int np = (n + 1) & ~1;
   const int npairs = np / 2;
   const int grp = tid / G, gl = tid % G;
   const double tol = fmax(1e-14, 8.0 * 2.220446049250313e-16 * n);
   const double tol2 = tol * tol;
+  const int m1 = np - 1;
   for (int sweep = 0; sweep < 30; ++sweep) {
-    double off2 = 0.0;
-    for (int rnd = 0; rnd < np - 1; ++rnd) {
-      int a = np - 1, b = rnd;
-      if (grp > 0) {
-        a = (rnd + grp) % (np - 1);
-        b = (rnd - grp + (np - 1)) % (np - 1);
-      }
+    int rotated = 0;
+    int a = grp == 0 ? m1 : grp % m1, b = grp == 0 ? 0 : (m1 - grp % m1) % m1;
+    for (int rnd = 0; rnd < m1; ++rnd) {
       if (grp < npairs && a < n && b < n) {
         const int pp = min(a, b), qq = max(a, b);
         double* __restrict__ Ap = A + pp * SM;
         double* __restrict__ Aq = A + qq * SM;
         double* __restrict__ Vp = V + pp * SM;
         double* __restrict__ Vq = V + qq * SM;
-        double xr[RU], yr[RU], vx[VREG ? RU : 1], vy[VREG ? RU : 1];
+        double xr[RU], yr[RU], vx[RU], vy[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
           const int i = gl + G * u;
           const bool in = i < n;
           xr[u] = in ? Ap[i] : 0.0;
           yr[u] = in ? Aq[i] : 0.0;
-          if (VREG) {
-            vx[u] = in ? Vp[i] : 0.0;
-            vy[u] = in ? Vq[i] : 0.0;
-          }
+          vx[u] = in ? Vp[i] : 0.0;
+          vy[u] = in ? Vq[i] : 0.0;
         }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -590,8 +696,8 @@ __device__ void jacobi_wave_rounds(double* A, double* V, int n, double thr2) {
         ga = group_sum<G>(ga);
         if (ga != 0.0 && al != 0.0 && be != 0.0 && (al >= thr2 || be >= thr2)) {
           const double g2 = ga * ga, ab = al * be;
-          off2 = fmax(off2, g2 / ab);
           if (g2 >= tol2 * ab) {
+            rotated = 1;
             double cs, sn;
             jacobi_rotation(al, be, ga, cs, sn);
 #pragma unroll
@@ -600,42 +706,36 @@ __device__ void jacobi_wave_rounds(double* A, double* V, int n, double thr2) {
               if (i < n) {
                 Ap[i] = cs * xr[u] - sn * yr[u];
                 Aq[i] = sn * xr[u] + cs * yr[u];
-                const double v1 = VREG ? vx[u] : Vp[i], v2 = VREG ? vy[u] : Vq[i];
-                Vp[i] = cs * v1 - sn * v2;
-                Vq[i] = sn * v1 + cs * v2;
+                Vp[i] = cs * vx[u] - sn * vy[u];
+                Vq[i] = sn * vx[u] + cs * vy[u];
               }
             }
           }
         }
       }
-      wave_sync_lds();
+      if (grp > 0) {
+        a = a + 1 == m1 ? 0 : a + 1;
+        b = b + 1 == m1 ? 0 : b + 1;
+      } else {
+        b += 1;
+      }
+      __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) off2 = fmax(off2, __shfl_xor(off2, o));
-    if (off2 < tol2) break;
+    if (!__syncthreads_or(rotated)) break;   // converged: no pair was rotated
   }
 }
 
-__device__ void jacobi_wave_core(double* A, double* V, int n, double thr2) {
-  // pairs * G <= 64 and RU * G >= n for each size class
-  // (V stays in LDS for the two largest classes to bound the register count)
-  if (n <= 2)
-    jacobi_wave_rounds<64, 1, true>(A, V, n, thr2);
-  else if (n <= 4)
-    jacobi_wave_rounds<32, 1, true>(A, V, n, thr2);
-  else if (n <= 8)
-    jacobi_wave_rounds<16, 1, true>(A, V, n, thr2);
-  else if (n <= 16)
-    jacobi_wave_rounds<8, 2, true>(A, V, n, thr2);
+__device__ void jacobi_wg(double* A, double* V, int n, double thr2) {
+  if (n <= 16)
+    jacobi_wg_rounds<16, 1>(A, V, n, thr2);
   else if (n <= 32)
-    jacobi_wave_rounds<4, 8, true>(A, V, n, thr2);
-  else if (n <= 48)
-    jacobi_wave_rounds<2, 24, false>(A, V, n, thr2);
+    jacobi_wg_rounds<16, 2>(A, V, n, thr2);
   else
-    jacobi_wave_rounds<2, 32, false>(A, V, n, thr2);
+    jacobi_wg_rounds<8, 8>(A, V, n, thr2);
 }
 
-// Work-group entry of the single-wave Jacobi (V := identity first).
-__device__ void jacobi_svd_wave(double* A, double* V, int n, double thr2, double* red) {
+// Work-group Jacobi for n <= 64 with V := identity first.
+__device__ void jacobi_svd_wg(double* A, double* V, int n, double thr2, double* red) {
   (void)red;
   const int tid = threadIdx.x;
   for (int e = tid; e < n * n; e += 256) {
@@ -643,7 +743,7 @@ __device__ void jacobi_svd_wave(double* A, double* V, int n, double thr2, double
     V[i + j * SM] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (tid < 64) jacobi_wave_core(A, V, n, thr2);
+  jacobi_wg(A, V, n, thr2);
   __syncthreads();
 }
 
@@ -889,6 +989,105 @@ __device__ int qrcp_wave(double* T, int n, double tau, int* piv, int* kout) {
   return k;
 }
 
+// Lane-private vectors of RU doubles with compile-time register indices:
+// an element at a run-time index is read or written by a select over all of
+// them (no dynamic register indexing).
+template <int RU>
+__device__ __forceinline__ double reg_get(const double (&r)[RU], int j) {
+  double x = 0.0;
+#pragma unroll
+  for (int u = 0; u < RU; ++u) x = (u == j) ? r[u] : x;
+  return x;
+}
+template <int RU>
+__device__ __forceinline__ void reg_set(double (&r)[RU], int j, double x) {
+#pragma unroll
+  for (int u = 0; u < RU; ++u) r[u] = (u == j) ? x : r[u];
+}
+
+// Second half for n <= RU: lane c < kk forms Z = Q2 V[:, ord[c]] in
+// registers (reflectors applied last to first, each read as a broadcast),
+// then C1[:, c] = R2^{-1} Z[:, c] by column-oriented back substitution.
+template <int RU>
+__device__ void sketch_f_out_reg(const double* V, const double* R1, const double* R2, const double* beta,
+                                 const int* ord, int n, int kk, double* __restrict__ C1, int rmax) {
+  const int c = threadIdx.x;
+  const bool act = c < kk;
+  const int oc = act ? ord[c] : 0;
+  double z[RU];
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    const double x = V[u + oc * SM];
+    z[u] = (act && u < n) ? x : 0.0;
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const double bj = beta[j];
+    if (bj == 0.0) continue;
+    const double v0 = beta[SM + j];
+    const int base = j * n - j * (j + 1) / 2 - j - 1;
+    double cv[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      const double r = R1[u > j ? base + u : 0];
+      cv[u] = (u == j) ? v0 : ((u > j && u < n) ? r : 0.0);
+    }
+    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) {
+      if (u % 4 == 0) d0 = fma(cv[u], z[u], d0);
+      if (u % 4 == 1) d1 = fma(cv[u], z[u], d1);
+      if (u % 4 == 2) d2 = fma(cv[u], z[u], d2);
+      if (u % 4 == 3) d3 = fma(cv[u], z[u], d3);
+    }
+    const double d = ((d0 + d1) + (d2 + d3)) * bj;
+#pragma unroll
+    for (int u = 0; u < RU; ++u) z[u] = fma(-d, cv[u], z[u]);
+  }
+#pragma unroll
+  for (int i = RU - 1; i >= 0; --i) {
+    if (i < n) {
+      const double* col = R2 + i * (i + 1) / 2;
+      const double d = col[i];
+      const double x = (d != 0.0) ? z[i] / d : 0.0;
+      z[i] = x;
+#pragma unroll
+      for (int u = 0; u < i; ++u) z[u] = fma(-col[u], x, z[u]);
+    }
+  }
+  if (act) {
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+      if (u < n) C1[u + (size_t)c * rmax] = z[u];
+  }
+}
+
+// C1 = Pi R'_k^{-1} for n <= RU by the first wave: lane c < k forms column c
+// of R'_k^{-1} in registers by column-oriented substitution from e_c (every
+// lane walks the same columns, so R' is read as a broadcast), then writes
+// row piv[i] of C1 for every i < n (zero for i > c).
+template <int RU>
+__device__ void sketch_p_inv_reg(const double* T, const int* piv, int n, int kk, double* __restrict__ C1, int rmax) {
+  const int c = threadIdx.x;
+  double x[RU];
+#pragma unroll
+  for (int u = 0; u < RU; ++u) x[u] = (u == c) ? 1.0 : 0.0;
+#pragma unroll
+  for (int l = RU - 1; l >= 0; --l) {
+    if (l < kk) {
+      const int pl = piv[l];
+      const double xl = x[l] / T[l * TLD + pl];
+      x[l] = xl;
+#pragma unroll
+      for (int u = 0; u < l; ++u) x[u] = fma(-T[u * TLD + pl], xl, x[u]);
+    }
+  }
+  if (c < kk) {
+#pragma unroll
+    for (int u = 0; u < RU; ++u)
+      if (u < n) C1[piv[u] + (size_t)c * rmax] = (u <= c) ? x[u] : 0.0;
+  }
+}
+
 // Householder QR of the n x n matrix M in LDS (ld SM) that keeps the
 // reflectors: on exit R is in the upper triangle, v_j below the diagonal of
 // column j with its leading entry in vtop[j], and H_j = I - beta[j] v_j v_j^T,
@@ -962,6 +1161,22 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
   load_upper(refp(bufs, J.R1), rmax, n, R1);
   if (J.kind != SK_SKETCH_P) load_upper(refp(bufs, J.R2), rmax, n, R2);
   __syncthreads();
+  if (J.kind == SK_SKETCH_P && n <= 32) {
+    // pivoted QR on R1 transposed into V (row i at V[i * TLD]), then the
+    // inverse with the columns in registers, both by the first wave
+    __shared__ int s_kr;
+    for (int e = tid; e < n * n; e += 256) {
+      int i = e / n, l = e % n;
+      V[i * TLD + l] = (i <= l) ? R1[upk(i, l)] : 0.0;
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int kk = qrcp_wave(V, n, eps, ord, &s_kr);
+      sketch_p_inv_reg<32>(V, ord, n, kk, C1, rmax);
+    }
+    if (tid == 0) dyn[J.out_rank_slot] = s_kr;
+    return;
+  }
   if (J.kind == SK_SKETCH_P && n <= 64) {
     // single-wave pivoted QR on R1 transposed into V (row i at V[i * TLD])
     __shared__ int s_k;
@@ -1021,11 +1236,10 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     return;
   }
   if (J.kind == SK_SKETCH_F && n <= 64) {
-    // The whole truncation by the first wave (lanes = rows of M = columns of
-    // M^T), phases ordered by wave-scope fences:
-    //   M = R1 R2^{-1};  M^T = Q2 R2' (Householder, reflectors kept);
-    //   one-sided Jacobi on B = R2'^T with V;  Z = Q2 V[:, ord];
-    //   C1 = R2^{-1} Z_k.
+    // The truncation: the first wave (lanes = rows of M = columns of M^T)
+    // forms M = R1 R2^{-1} and M^T = Q2 R2' (Householder, reflectors kept);
+    // the work-group runs one-sided Jacobi on B = R2'^T with V; the first
+    // wave forms Z = Q2 V[:, ord] and C1 = R2^{-1} Z_k.
     __shared__ int s_kk;
     if (tid < 64) {
       const int lane = tid;
@@ -1073,17 +1287,21 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
         }
       }
       wave_sync_lds();   // rows of A read below were zeroed by other lanes
-      for (int e = lane; e < n * n; e += 64) {
-        const int i = e % n, j = e / n;
-        V[i + j * SM] = (i == j) ? 1.0 : 0.0;
-      }
-      double f2 = 0.0;
-      if (lane < n)
-        for (int c = 0; c < n; ++c) f2 = fma(A[lane + c * SM], A[lane + c * SM], f2);
-      for (int o = 32; o > 0; o >>= 1) f2 += __shfl_xor(f2, o);
-      wave_sync_lds();
+    }
+    // one-sided Jacobi on B by the whole work-group
+    __syncthreads();
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e % n, j = e / n;
+      V[i + j * SM] = (i == j) ? 1.0 : 0.0;
+    }
+    {
+      const double f2 = fro2_lds(A, n, red);
       const double dt = 1e-3 * eps;
-      jacobi_wave_core(A, V, n, dt * dt * f2);
+      jacobi_wg(A, V, n, dt * dt * f2);
+    }
+    __syncthreads();
+    if (tid < 64) {
+      const int lane = tid;
       // singular values and their order (ties to the lower index)
       if (lane < n) {
         double q = 0.0;
@@ -1114,31 +1332,35 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
         kk = J.cap;
       }
       if (J.sat.maxv >= 0 && kk >= dimv(dyn, J.sat) && lane == 0) atomicOr(status, STAT_SKETCH_SAT);
-      // Z = Q2 V[:, ord[c]] (lane c, row i at A[i * TLD + c]); A is free now
-      const int c = lane;
-      if (c < kk)
-        for (int i = 0; i < n; ++i) A[i * TLD + c] = V[i + ord[c] * SM];
-      for (int j = n - 1; j >= 0; --j) {
-        const double bj = beta[j];
-        if (c < kk && bj != 0.0) {
-          const double* vj = R1 + j * n - j * (j + 1) / 2;
-          const double v0 = beta[SM + j];
-          double d = v0 * A[j * TLD + c];
-          for (int i = j + 1; i < n; ++i) d = fma(vj[i - j - 1], A[i * TLD + c], d);
-          d *= bj;
-          A[j * TLD + c] -= d * v0;
-          for (int i = j + 1; i < n; ++i) A[i * TLD + c] -= d * vj[i - j - 1];
+      if (n <= 32) {
+        sketch_f_out_reg<32>(V, R1, R2, beta, ord, n, kk, C1, rmax);
+      } else {
+        // Z = Q2 V[:, ord[c]] (lane c, row i at A[i * TLD + c]); A is free now
+        const int c = lane;
+        if (c < kk)
+          for (int i = 0; i < n; ++i) A[i * TLD + c] = V[i + ord[c] * SM];
+        for (int j = n - 1; j >= 0; --j) {
+          const double bj = beta[j];
+          if (c < kk && bj != 0.0) {
+            const double* vj = R1 + j * n - j * (j + 1) / 2;
+            const double v0 = beta[SM + j];
+            double d = v0 * A[j * TLD + c];
+            for (int i = j + 1; i < n; ++i) d = fma(vj[i - j - 1], A[i * TLD + c], d);
+            d *= bj;
+            A[j * TLD + c] -= d * v0;
+            for (int i = j + 1; i < n; ++i) A[i * TLD + c] -= d * vj[i - j - 1];
+          }
         }
-      }
-      // C1 = R2^{-1} Z_k by back substitution in place
-      if (c < kk) {
-        for (int i = n - 1; i >= 0; --i) {
-          double acc = A[i * TLD + c];
-          for (int l = i + 1; l < n; ++l) acc = fma(-R2[upk(i, l)], A[l * TLD + c], acc);
-          const double d = R2[upk(i, i)];
-          const double x = (d != 0.0) ? acc / d : 0.0;
-          A[i * TLD + c] = x;
-          C1[i + (size_t)c * rmax] = x;
+        // C1 = R2^{-1} Z_k by back substitution in place
+        if (c < kk) {
+          for (int i = n - 1; i >= 0; --i) {
+            double acc = A[i * TLD + c];
+            for (int l = i + 1; l < n; ++l) acc = fma(-R2[upk(i, l)], A[l * TLD + c], acc);
+            const double d = R2[upk(i, i)];
+            const double x = (d != 0.0) ? acc / d : 0.0;
+            A[i * TLD + c] = x;
+            C1[i + (size_t)c * rmax] = x;
+          }
         }
       }
       if (lane == 0) s_kk = kk;
@@ -1192,7 +1414,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     const double f2 = fro2_lds(A, n, red);
     const double dt = 1e-3 * eps;
     if (n <= 64)
-      jacobi_svd_wave(A, V, n, dt * dt * f2, red);
+      jacobi_svd_wg(A, V, n, dt * dt * f2, red);
     else
       jacobi_svd_lds(A, V, n, dt * dt * f2, red);
   }
