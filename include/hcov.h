@@ -82,6 +82,10 @@ typedef struct {
   hcov_alloc_fn alloc;    /* optional device allocator; NULL = hipMalloc */
   hcov_free_fn free;
   void* alloc_user;
+  int use_graphs;         /* 1: the factorisation sweep is captured once as a
+                             HIP graph on a stream of the context and replayed
+                             by later factorisations (default 1); 0: every
+                             stage is launched separately */
 } hcov_opts;
 
 /* Structure and work counters of a context (see hcov_stats). */
@@ -100,6 +104,7 @@ typedef struct {
   double ms_tree, ms_assemble, ms_factor, ms_solve;   /* last phase times */
   int64_t n_steps;            /* sweep steps of the factorisation (= 2^D) */
   int64_t n_launches_factor;  /* kernel launches of one factorisation */
+  int64_t n_graph_replays;    /* factorisations run as a replay of the captured sweep */
 } hcov_stats_t;
 
 typedef struct hcov_ctx hcov_ctx;

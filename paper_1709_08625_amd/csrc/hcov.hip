@@ -60,6 +60,13 @@ struct hcov_ctx {
   // second lane of the factorisation sweep (see ST_FORK / ST_JOIN)
   hipStream_t stream2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // the sweep captured as a graph (index 1: with the fused right-hand side),
+  // replayed on gstream between two events of the caller's stream
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::vector<hipGraphExec_t> gexec[2];   // segments of whole steps, replayed in order
+  bool graph_failed = false;
+  int64_t n_replays = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   std::vector<Stage> prof_stages;
   // state
@@ -302,6 +309,50 @@ int reduce_dev(hcov_ctx* c, const double* x, int64_t n, int mode, double* out) {
   return HCOV_OK;
 }
 
+// Captures the launches of the sweep (both lanes, joined by the fork/join
+// events) on gstream into graphs of whole steps, each of at most
+// GRAPH_STAGES stages (a graph is one long dependency chain; bounded
+// segments keep the runtime's per-graph work bounded).  Kernel arguments are
+// fixed for the life of the context (sizes that change with theta live in
+// device memory), so the segments serve every later factorisation.  Any
+// failure leaves the context on per-stage launches.
+constexpr size_t GRAPH_STAGES = 1500;
+
+void capture_sweep(hcov_ctx* c, const std::vector<std::vector<Stage>>& steps, int gi) {
+  hipStream_t user = c->stream;
+  c->stream = c->gstream;
+  bool ok = true;
+  size_t j = 0;
+  while (ok && j < steps.size()) {
+    if (hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      ok = false;
+      break;
+    }
+    size_t staged = 0;
+    while (j < steps.size() && (staged == 0 || staged + steps[j].size() <= GRAPH_STAGES)) {
+      if (run_stages(c, steps[j]) != HCOV_OK) ok = false;
+      staged += steps[j].size();
+      ++j;
+      if (!ok) break;
+    }
+    hipGraph_t g = nullptr;
+    const bool ended = hipStreamEndCapture(c->gstream, &g) == hipSuccess;
+    hipGraphExec_t ge = nullptr;
+    ok = ok && ended && g && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
+    if (g) (void)hipGraphDestroy(g);
+    if (ok) c->gexec[gi].push_back(ge);
+  }
+  c->stream = user;
+  if (!ok) {
+    for (auto ge : c->gexec[gi])
+      if (ge) (void)hipGraphExecDestroy(ge);
+    c->gexec[gi].clear();
+    c->graph_failed = true;
+    c->err.clear();
+    (void)hipGetLastError();
+  }
+}
+
 int factor(hcov_ctx* c, const double* z_dev_cluster, bool fuse) {
   if (!c->assembled) return fail(c, HCOV_ESTATE, "matrix not assembled");
   double t0 = now_ms();
@@ -309,9 +360,20 @@ int factor(hcov_ctx* c, const double* z_dev_cluster, bool fuse) {
   if (r) return r;
   (void)z_dev_cluster;   // with fuse, the right-hand side is already in B_RHS
   const auto& steps = fuse ? c->plan.steps : c->plan.steps_nofuse;
-  for (const auto& st : steps) {
-    r = run_stages(c, st);
-    if (r) return r;
+  const int gi = fuse ? 1 : 0;
+  if (c->gstream && c->prof_kind < 0 && !c->graph_failed && c->gexec[gi].empty()) capture_sweep(c, steps, gi);
+  if (c->gstream && c->prof_kind < 0 && !c->gexec[gi].empty()) {
+    HIPCHK(c, hipEventRecord(c->ev_in, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->gstream, c->ev_in, 0));
+    for (auto ge : c->gexec[gi]) HIPCHK(c, hipGraphLaunch(ge, c->gstream));
+    c->n_replays += 1;
+    HIPCHK(c, hipEventRecord(c->ev_out, c->gstream));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_out, 0));
+  } else {
+    for (const auto& st : steps) {
+      r = run_stages(c, st);
+      if (r) return r;
+    }
   }
   c->assembled = false;   // C~ is overwritten by the factor
   r = check_status(c, true);
@@ -361,6 +423,7 @@ void hcov_opts_default(hcov_opts* o) {
   o->max_rank = 64;
   o->aca_eps_factor = 0.1;
   o->fuse_solve = 1;
+  o->use_graphs = 1;
 }
 
 const char* hcov_strerror(int code) {
@@ -398,9 +461,15 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   c->stream = (hipStream_t)hip_stream;
   if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+      (o.use_graphs && (hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking) != hipSuccess ||
+                        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+                        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess))) {
     if (c->stream2) (void)hipStreamDestroy(c->stream2);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     delete c;
     return HCOV_EDEVICE;
   }
@@ -741,6 +810,7 @@ int hcov_stats(const hcov_ctx* c, hcov_stats_t* s) {
   s->ms_solve = c->ms_solve;
   s->n_steps = int64_t(1) << c->D;
   s->n_launches_factor = P.n_launch_fact;
+  s->n_graph_replays = c->n_replays;
   // ranks
   std::vector<int> dyn(P.n_dyn + 1);
   if (hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
@@ -806,11 +876,18 @@ int hcov_tree_dump(const hcov_ctx* c, double* bbox, int64_t* blocks) {
 void hcov_destroy(hcov_ctx* c) {
   if (!c) return;
   if (c->stream2) (void)hipStreamSynchronize(c->stream2);
+  if (c->gstream) (void)hipStreamSynchronize(c->gstream);
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
+  for (auto& v : c->gexec)
+    for (auto g : v)
+      if (g) (void)hipGraphExecDestroy(g);
   if (c->stream2) (void)hipStreamDestroy(c->stream2);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   for (void* p : c->allocs) {
     if (c->opts.free)
       c->opts.free(p, c->opts.alloc_user);

@@ -128,6 +128,7 @@ struct hcov_server {
         o.alloc = async_alloc;
         o.free = async_free;
         o.alloc_user = (void*)st;
+        o.use_graphs = 0;   // a one-shot context would not replay a captured sweep
         hcov_ctx* c = nullptr;
         int rc = hcov_build(r.locs.data(), r.n, r.theta, r.eps, r.leaf, r.eta, &o, (void*)st, &c);
         if (rc == HCOV_OK || rc == HCOV_ERANK) {

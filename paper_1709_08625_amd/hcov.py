@@ -39,7 +39,7 @@ class Result(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("max_rank", C.c_int), ("aca_eps_factor", C.c_double),
                 ("fuse_solve", C.c_int), ("mem_cap_bytes", C.c_size_t), ("alloc", ALLOC_FN),
-                ("free", FREE_FN), ("alloc_user", C.c_void_p)]
+                ("free", FREE_FN), ("alloc_user", C.c_void_p), ("use_graphs", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -48,7 +48,7 @@ class Stats(C.Structure):
                 ("max_rank_seen", C.c_int), ("mean_rank", C.c_double), ("bytes_device", C.c_int64),
                 ("bytes_factor", C.c_int64), ("ms_tree", C.c_double), ("ms_assemble", C.c_double),
                 ("ms_factor", C.c_double), ("ms_solve", C.c_double), ("n_steps", C.c_int64),
-                ("n_launches_factor", C.c_int64)]
+                ("n_launches_factor", C.c_int64), ("n_graph_replays", C.c_int64)]
 
 
 _lib = None
