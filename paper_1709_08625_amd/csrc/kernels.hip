@@ -357,6 +357,37 @@ __global__ __launch_bounds__(256) void k_gemm(const Bufs* __restrict__ bufs, con
 constexpr int QR_LDS = 160 * 96;     // doubles of the LDS matrix buffer
 constexpr int QR_CMAX = 96;          // max columns
 
+// Cross-lane moves inside a row of 16 lanes (DPP: a plain vector
+// instruction, no LDS round trip), applied to both halves of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8
+constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15 - i within 16
+
+__device__ __forceinline__ double wave_bcast(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Sum over the 64 lanes of a wave, the same bits in every lane: DPP moves
+// inside each row of 16 lanes, then the four row totals read as scalars.
+__device__ __forceinline__ double wave_sum64(double v) {
+  v += dpp_move<DPP_MIRROR>(v);
+  v += dpp_move<DPP_HALF_MIRROR>(v);
+  v += dpp_move<DPP_XOR2>(v);
+  v += dpp_move<DPP_XOR1>(v);
+  return (wave_bcast(v, 0) + wave_bcast(v, 16)) + (wave_bcast(v, 32) + wave_bcast(v, 48));
+}
+
 __device__ void house_qr_lds(double* M, int ldm, int mrows, int c, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int j = 0; j < c && j < mrows; ++j) {
@@ -366,7 +397,7 @@ __device__ void house_qr_lds(double* M, int ldm, int mrows, int c, double* red) 
         double v = M[i + j * ldm];
         s += v * v;
       }
-      for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+      s = wave_sum64(s);
       if (lane == 0) {
         double nrm = sqrt(s);
         double a = M[j + j * ldm];
@@ -380,12 +411,26 @@ __device__ void house_qr_lds(double* M, int ldm, int mrows, int c, double* red) 
     __syncthreads();
     const double beta = red[1];
     if (beta != 0.0) {
-      for (int l = j + 1 + wave; l < c; l += 4) {
-        double sdot = 0.0;
-        for (int i = j + lane; i < mrows; i += 64) sdot += M[i + j * ldm] * M[i + l * ldm];
-        for (int o = 32; o > 0; o >>= 1) sdot += __shfl_xor(sdot, o);
-        sdot *= beta;
-        for (int i = j + lane; i < mrows; i += 64) M[i + l * ldm] -= sdot * M[i + j * ldm];
+      // wave w updates columns j + 1 + w + 4 t, four at a time so that their
+      // reductions overlap
+      for (int l0 = j + 1 + wave; l0 < c; l0 += 16) {
+        double sd[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int l = l0 + 4 * t;
+          double s = 0.0;
+          if (l < c)
+            for (int i = j + lane; i < mrows; i += 64) s += M[i + j * ldm] * M[i + l * ldm];
+          sd[t] = s;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) sd[t] = wave_sum64(sd[t]) * beta;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int l = l0 + 4 * t;
+          if (l < c)
+            for (int i = j + lane; i < mrows; i += 64) M[i + l * ldm] -= sd[t] * M[i + j * ldm];
+        }
       }
     }
     __syncthreads();
@@ -621,20 +666,6 @@ __device__ __forceinline__ void jacobi_rotation(double al, double be, double ga,
   cs = rsq_nr(fma(tt, tt, 1.0));
   sn = cs * tt;
 }
-
-// Cross-lane moves inside a row of 16 lanes (DPP: a plain vector
-// instruction, no LDS round trip), applied to both halves of a double.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
-constexpr int DPP_XOR2 = 0x4E;          // quad_perm [2,3,0,1]
-constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within 8
-constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15 - i within 16
 
 // Sum over an aligned group of G lanes; every lane of the group gets the
 // same bits (each level adds a lane's value to its partner's, and the
@@ -1494,12 +1525,6 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
 
 // ------------------------------------------------------------------ leaf
 // value of v in lane `lane` (uniform) of the wave
-__device__ __forceinline__ double wave_bcast(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffLL), lane);
-  const int hi = __builtin_amdgcn_readlane(int(b >> 32), lane);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
 
 // Diagonal leaf factorisation (potrf, lower) of an updated tile of order
 // p <= 128.  Each thread owns an 8 x 8 block of the tile in registers (rows
