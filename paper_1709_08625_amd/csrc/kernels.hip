@@ -434,10 +434,11 @@ __device__ void house_qr_lds(double* M, int ldm, int mrows, int c, double* red) 
       }
     }
     __syncthreads();
+    // column j is final; the next column's steps touch only columns > j
     if (tid == 0) M[j + j * ldm] = red[0];
     for (int i = j + 1 + tid; i < mrows; i += 256) M[i + j * ldm] = 0.0;
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 __device__ __forceinline__ int qr_ldm(int c) { return QR_LDS / (c > 0 ? c : 1); }
@@ -696,7 +697,7 @@ __device__ void jacobi_wg_rounds(double* A, double* V, int n, double thr2) {
   const double tol2 = tol * tol;
   const int m1 = np - 1;
   for (int sweep = 0; sweep < 30; ++sweep) {
-    int rotated = 0;
+    int big = 0;
     int a = grp == 0 ? m1 : grp % m1, b = grp == 0 ? 0 : (m1 - grp % m1) % m1;
     for (int rnd = 0; rnd < m1; ++rnd) {
       if (grp < npairs && a < n && b < n) {
@@ -728,7 +729,7 @@ __device__ void jacobi_wg_rounds(double* A, double* V, int n, double thr2) {
         if (ga != 0.0 && al != 0.0 && be != 0.0 && (al >= thr2 || be >= thr2)) {
           const double g2 = ga * ga, ab = al * be;
           if (g2 >= tol2 * ab) {
-            rotated = 1;
+            if (g2 >= tol * ab) big = 1;
             double cs, sn;
             jacobi_rotation(al, be, ga, cs, sn);
 #pragma unroll
@@ -752,7 +753,9 @@ __device__ void jacobi_wg_rounds(double* A, double* V, int n, double thr2) {
       }
       __syncthreads();
     }
-    if (!__syncthreads_or(rotated)) break;   // converged: no pair was rotated
+    // converged once no pair of a sweep had a cosine above sqrt(tol): the
+    // convergence is quadratic, so what this sweep left is of order tol
+    if (!__syncthreads_or(big)) break;
   }
 }
 
@@ -1129,7 +1132,7 @@ __device__ void house_qr_keep(double* M, int n, double* vtop, double* beta, doub
     if (wave == 0) {
       double sq = 0.0;
       for (int i = j + lane; i < n; i += 64) sq += M[i + j * SM] * M[i + j * SM];
-      for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+      sq = wave_sum64(sq);
       if (lane == 0) {
         const double nrm = sqrt(sq);
         const double a = M[j + j * SM];
@@ -1143,22 +1146,36 @@ __device__ void house_qr_keep(double* M, int n, double* vtop, double* beta, doub
     __syncthreads();
     const double b = red[1];
     if (b != 0.0) {
-      for (int l = j + 1 + wave; l < n; l += 4) {
-        double sdot = 0.0;
-        for (int i = j + lane; i < n; i += 64) sdot += M[i + j * SM] * M[i + l * SM];
-        for (int o = 32; o > 0; o >>= 1) sdot += __shfl_xor(sdot, o);
-        sdot *= b;
-        for (int i = j + lane; i < n; i += 64) M[i + l * SM] -= sdot * M[i + j * SM];
+      // wave w updates columns j + 1 + w + 4 t, four at a time
+      for (int l0 = j + 1 + wave; l0 < n; l0 += 16) {
+        double sd[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int l = l0 + 4 * t;
+          double sdot = 0.0;
+          if (l < n)
+            for (int i = j + lane; i < n; i += 64) sdot += M[i + j * SM] * M[i + l * SM];
+          sd[t] = sdot;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) sd[t] = wave_sum64(sd[t]) * b;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int l = l0 + 4 * t;
+          if (l < n)
+            for (int i = j + lane; i < n; i += 64) M[i + l * SM] -= sd[t] * M[i + j * SM];
+        }
       }
     }
     __syncthreads();
+    // column j is final; the next column's steps touch only columns > j
     if (tid == 0) {
       vtop[j] = M[j + j * SM];
       beta[j] = b;
       M[j + j * SM] = red[0];
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // Small dense problems built from upper-triangular R factors.
@@ -1267,10 +1284,10 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     return;
   }
   if (J.kind == SK_SKETCH_F && n <= 64) {
-    // The truncation: the first wave (lanes = rows of M = columns of M^T)
-    // forms M = R1 R2^{-1} and M^T = Q2 R2' (Householder, reflectors kept);
-    // the work-group runs one-sided Jacobi on B = R2'^T with V; the first
-    // wave forms Z = Q2 V[:, ord] and C1 = R2^{-1} Z_k.
+    // The truncation: the first wave (lane = row) forms M = R1 R2^{-1}; the
+    // work-group forms M^T = Q2 R2' (Householder, reflectors kept) and runs
+    // one-sided Jacobi on B = R2'^T with V; the first wave forms
+    // Z = Q2 V[:, ord] and C1 = R2^{-1} Z_k.
     __shared__ int s_kk;
     if (tid < 64) {
       const int lane = tid;
@@ -1283,42 +1300,22 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
           A[lane + j * SM] = (d != 0.0) ? acc / d : 0.0;
         }
       }
-      wave_sync_lds();
-      // Householder QR of T = M^T: T[i][l] = A[l + i * SM], lane l owns column l
-      for (int j = 0; j < n; ++j) {
-        double sq = 0.0;
-        for (int i = j; i < n; ++i) sq = fma(A[j + i * SM], A[j + i * SM], sq);
-        const double nrm = sqrt(sq);
-        const double a = A[j + j * SM];
-        const double alpha = (a >= 0.0) ? -nrm : nrm;
-        const double vtv = 2.0 * nrm * (nrm + fabs(a));
-        const double bj = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-        const double vj = a - alpha;
-        if (lane > j && lane < n && bj != 0.0) {
-          double w = vj * A[lane + j * SM];
-          for (int i = j + 1; i < n; ++i) w = fma(A[j + i * SM], A[lane + i * SM], w);
-          w *= bj;
-          A[lane + j * SM] -= w * vj;
-          for (int i = j + 1; i < n; ++i) A[lane + i * SM] -= w * A[j + i * SM];
-        }
-        if (lane == j) {
-          A[j + j * SM] = alpha;
-          beta[j] = bj;
-          beta[SM + j] = vj;
-        }
-        wave_sync_lds();
-      }
-      // reflector j (rows i > j of T's column j = A[j + i * SM], the strict
-      // upper triangle of A) to R1's packed storage; A keeps B = R2'^T
-      for (int j = 0; j < n; ++j) {
-        const int i = lane;
-        if (i > j && i < n) {
-          R1[j * n - j * (j + 1) / 2 + (i - j - 1)] = A[j + i * SM];
-          A[j + i * SM] = 0.0;
-        }
-      }
-      wave_sync_lds();   // rows of A read below were zeroed by other lanes
     }
+    // M^T = Q2 R2' by the work-group (reflectors kept), then the reflector
+    // tails to R1's packed storage (free now) and B = R2'^T into A
+    __syncthreads();
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e % n, j = e / n;
+      V[i + j * SM] = A[j + i * SM];
+    }
+    __syncthreads();
+    house_qr_keep(V, n, sv, beta, red);
+    for (int e = tid; e < n * n; e += 256) {
+      const int i = e % n, j = e / n;
+      if (i > j) R1[j * n - j * (j + 1) / 2 + (i - j - 1)] = V[i + j * SM];
+      A[i + j * SM] = (i >= j) ? V[j + i * SM] : 0.0;
+    }
+    for (int j = tid; j < n; j += 256) beta[SM + j] = sv[j];
     // one-sided Jacobi on B by the whole work-group
     __syncthreads();
     for (int e = tid; e < n * n; e += 256) {

@@ -647,8 +647,14 @@ class Builder {
   // right-hand side, while the first lane recompresses the new low-rank
   // targets: the two sets of work touch disjoint data.
   void fork_leaf(int64_t j, const std::vector<std::pair<int32_t, std::vector<Term>>>& dns,
-                 const std::vector<int32_t>& fresh, bool fuse_rhs, std::vector<Stage>& st) {
+                 const std::vector<int32_t>& fresh, bool fuse_rhs, std::vector<Stage>& st,
+                 std::vector<Deferred>& dense_upd) {
     st.push_back(Stage{ST_FORK, 0, 0});
+    // the dense targets (the diagonal leaf among them) are updated on the
+    // second lane, ahead of the leaf factorisation
+    cur_lane = 1;
+    emit(dense_upd, st);
+    cur_lane = 0;
     const BlockInfo& B = P.blocks[P.diag_block[j]];
     LeafJob J{};
     J.D = Ref{B_DENSE, int32_t(B.r1 - B.r0), B.off_d};
@@ -735,21 +741,19 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
     emit(listB, st);   // W accumulation and U*core
 
     // ---- dense targets: D -= sum of the update terms, as GEMM jobs on the
-    // target tile (split into partial sums by emit() when long); they go into
-    // the same launch as the first sketch products
+    // target tile (split into partial sums by emit() when long); they run on
+    // the second lane (fork_leaf) while this lane forms the sketches
+    std::vector<Deferred> listD;
     for (auto& dt : dns) {
       if (dt.second.empty()) continue;
       const BlockInfo& B = P.blocks[dt.first];
       const int p = int(B.r1 - B.r0), q = int(B.c1 - B.c0);
-      int32_t d = defer(listA, Ref{B_DENSE, p, B.off_d}, dim_static(p), dim_static(q), 0);
+      int32_t d = defer(listD, Ref{B_DENSE, p, B.off_d}, dim_static(p), dim_static(q), 0);
       for (auto& T : dt.second)
-        dprod(listA[d], T.U.ref, 0, T.V.ref, 1, T.U.cols, int(T.r0 - B.r0), int(T.p0 - B.c0),
+        dprod(listD[d], T.U.ref, 0, T.V.ref, 1, T.U.cols, int(T.r0 - B.r0), int(T.p0 - B.c0),
               dim_static(int(T.r1 - T.r0)), dim_static(int(T.p1 - T.p0)), -1.0);
     }
-    if (lrs.empty()) {
-      emit(listA, st);
-      fork_leaf(j, dns, lrs_ids(lrs), fuse_rhs, st);
-    }
+    if (lrs.empty()) fork_leaf(j, dns, lrs_ids(lrs), fuse_rhs, st, listD);
 
     // ---- randomised recompression of low-rank targets
     if (!lrs.empty()) {
@@ -796,8 +800,8 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
                 dim_static(int(T.p1 - T.p0)), 0, 0, T.V.cols, s.r, 1.0);
         }
       }
+      fork_leaf(j, dns, lrs_ids(lrs), fuse_rhs, st, listD);
       emit(listA, st);
-      fork_leaf(j, dns, lrs_ids(lrs), fuse_rhs, st);
       // Y = U_A P1_A - sum U_t P1_t
       for (size_t t = 0; t < lrs.size(); ++t) {
         const BlockInfo& B = P.blocks[sk[t].b];
