@@ -388,6 +388,15 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return (wave_bcast(v, 0) + wave_bcast(v, 16)) + (wave_bcast(v, 32) + wave_bcast(v, 48));
 }
 
+// Largest value over the 64 lanes of a wave (NaN ignored), in every lane.
+__device__ __forceinline__ double wave_max64(double v) {
+  v = fmax(v, dpp_move<DPP_MIRROR>(v));
+  v = fmax(v, dpp_move<DPP_HALF_MIRROR>(v));
+  v = fmax(v, dpp_move<DPP_XOR2>(v));
+  v = fmax(v, dpp_move<DPP_XOR1>(v));
+  return fmax(fmax(wave_bcast(v, 0), wave_bcast(v, 16)), fmax(wave_bcast(v, 32), wave_bcast(v, 48)));
+}
+
 __device__ void house_qr_lds(double* M, int ldm, int mrows, int c, double* red) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int j = 0; j < c && j < mrows; ++j) {
@@ -969,22 +978,28 @@ __device__ int qrcp_wave(double* T, int n, double tau, int* piv, int* kout) {
   double r0 = 0.0;
   int k = n;
   for (int j = 0; j < n; ++j) {
-    // pivot: the largest remaining norm, ties to the lowest column
-    double bv = active ? cn : -1.0;
-    int bi = lane;
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ov = __shfl_xor(bv, o);
-      const int oi = __shfl_xor(bi, o);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
-        bi = oi;
-      }
+    // pivot: the largest remaining norm, ties to the lowest column (a wave
+    // max-reduction, then the lowest lane holding the maximum)
+    const double bv = active ? cn : -1.0;
+    const double mx = wave_max64(bv);
+    const unsigned long long hit = __ballot(active && bv == mx);
+    if (hit == 0ull) {   // only NaN norms remain
+      k = j;
+      break;
     }
-    const int p = bi;
-    // exact norm of the pivot column below row j (broadcast reads)
-    double sq = 0.0;
-    for (int i = j; i < n; ++i) sq = fma(T[i * TLD + p], T[i * TLD + p], sq);
-    const double nrm = sqrt(sq);
+    const int p = __ffsll((long long)hit) - 1;
+    // exact norm of the pivot column below row j (broadcast reads, four
+    // partial sums)
+    double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+    int i = j;
+    for (; i + 3 < n; i += 4) {
+      q0 = fma(T[i * TLD + p], T[i * TLD + p], q0);
+      q1 = fma(T[(i + 1) * TLD + p], T[(i + 1) * TLD + p], q1);
+      q2 = fma(T[(i + 2) * TLD + p], T[(i + 2) * TLD + p], q2);
+      q3 = fma(T[(i + 3) * TLD + p], T[(i + 3) * TLD + p], q3);
+    }
+    for (; i < n; ++i) q0 = fma(T[i * TLD + p], T[i * TLD + p], q0);
+    const double nrm = sqrt((q0 + q1) + (q2 + q3));
     if (j == 0) r0 = nrm;
     if (!(nrm > tau * r0) || !(nrm > 0.0)) {
       k = j;
@@ -996,16 +1011,23 @@ __device__ int qrcp_wave(double* T, int n, double tau, int* piv, int* kout) {
     const double vj = a - alpha;
     if (lane == p) active = false;
     if (active) {
-      double w = vj * T[j * TLD + lane];
-      for (int i = j + 1; i < n; ++i) w = fma(T[i * TLD + p], T[i * TLD + lane], w);
-      w *= beta;
+      double w0 = vj * T[j * TLD + lane], w1 = 0.0, w2 = 0.0, w3 = 0.0;
+      int i2 = j + 1;
+      for (; i2 + 3 < n; i2 += 4) {
+        w0 = fma(T[i2 * TLD + p], T[i2 * TLD + lane], w0);
+        w1 = fma(T[(i2 + 1) * TLD + p], T[(i2 + 1) * TLD + lane], w1);
+        w2 = fma(T[(i2 + 2) * TLD + p], T[(i2 + 2) * TLD + lane], w2);
+        w3 = fma(T[(i2 + 3) * TLD + p], T[(i2 + 3) * TLD + lane], w3);
+      }
+      for (; i2 < n; ++i2) w0 = fma(T[i2 * TLD + p], T[i2 * TLD + lane], w0);
+      const double w = ((w0 + w1) + (w2 + w3)) * beta;
       T[j * TLD + lane] -= w * vj;
-      for (int i = j + 1; i < n; ++i) T[i * TLD + lane] -= w * T[i * TLD + p];
+      for (int i3 = j + 1; i3 < n; ++i3) T[i3 * TLD + lane] -= w * T[i3 * TLD + p];
       const double r = T[j * TLD + lane];
       double c = cn - r * r;
       if (!(c > 1e-8 * cn0)) {
         c = 0.0;
-        for (int i = j + 1; i < n; ++i) c = fma(T[i * TLD + lane], T[i * TLD + lane], c);
+        for (int i3 = j + 1; i3 < n; ++i3) c = fma(T[i3 * TLD + lane], T[i3 * TLD + lane], c);
         cn0 = c;
       }
       cn = c;
@@ -1292,12 +1314,21 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     if (tid < 64) {
       const int lane = tid;
       // M column by column (col-major in A); a lane reads only its own row
+      // (four partial sums per entry)
       for (int j = 0; j < n; ++j) {
         if (lane < n) {
-          double acc = (lane <= j) ? R1[upk(lane, j)] : 0.0;
-          for (int l = 0; l < j; ++l) acc = fma(-A[lane + l * SM], R2[upk(l, j)], acc);
-          const double d = R2[upk(j, j)];
-          A[lane + j * SM] = (d != 0.0) ? acc / d : 0.0;
+          const double* col = R2 + j * (j + 1) / 2;   // column j of R2 (rows <= j)
+          double a0 = (lane <= j) ? R1[upk(lane, j)] : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+          int l = 0;
+          for (; l + 3 < j; l += 4) {
+            a0 = fma(-A[lane + l * SM], col[l], a0);
+            a1 = fma(-A[lane + (l + 1) * SM], col[l + 1], a1);
+            a2 = fma(-A[lane + (l + 2) * SM], col[l + 2], a2);
+            a3 = fma(-A[lane + (l + 3) * SM], col[l + 3], a3);
+          }
+          for (; l < j; ++l) a0 = fma(-A[lane + l * SM], col[l], a0);
+          const double d = col[j];
+          A[lane + j * SM] = (d != 0.0) ? ((a0 + a1) + (a2 + a3)) / d : 0.0;
         }
       }
     }
