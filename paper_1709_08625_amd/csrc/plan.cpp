@@ -188,7 +188,31 @@ class Builder {
     pending_prods.clear();
     job_base = int32_t(P.gjobs.size());
     int32_t t1 = int32_t(P.gtiles.size());
-    if (t1 > t0) out.push_back(Stage{ST_GEMM, t0, t1, cur_lane});
+    if (t1 > t0) {
+      // heaviest tiles first: work-groups start in tile order, so a launch
+      // with more tiles than resident work-groups is scheduled longest first
+      std::vector<std::pair<int, int32_t>> cost;
+      cost.reserve(size_t(t1 - t0));
+      for (int32_t t = t0; t < t1; ++t) {
+        const GemmTile& T = P.gtiles[t];
+        const GemmJob& g = P.gjobs[T.job];
+        int c = 0;
+        for (int32_t q = g.p0; q < g.p1; ++q) {
+          const GemmProd& pr = P.gprods[q];
+          const int i1 = pr.i0 + pr.mi.maxv, j1 = pr.j0 + pr.nj.maxv;
+          if (i1 <= T.ti * TM || pr.i0 >= (T.ti + 1) * TM || j1 <= T.tj * TN || pr.j0 >= (T.tj + 1) * TN) continue;
+          c += pr.tb == 2 ? 1 : chunks(est_k(pr.k));
+        }
+        cost.emplace_back(-c, t);
+      }
+      std::stable_sort(cost.begin(), cost.end(),
+                       [](const std::pair<int, int32_t>& x, const std::pair<int, int32_t>& y) { return x.first < y.first; });
+      std::vector<GemmTile> sorted;
+      sorted.reserve(cost.size());
+      for (auto& ct : cost) sorted.push_back(P.gtiles[ct.second]);
+      std::copy(sorted.begin(), sorted.end(), P.gtiles.begin() + t0);
+      out.push_back(Stage{ST_GEMM, t0, t1, cur_lane});
+    }
   }
 
   // ---------------------------------------------------------------- TSQR
