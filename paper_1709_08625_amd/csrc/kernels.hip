@@ -397,57 +397,137 @@ __device__ __forceinline__ double wave_max64(double v) {
   return fmax(fmax(wave_bcast(v, 0), wave_bcast(v, 16)), fmax(wave_bcast(v, 32), wave_bcast(v, 48)));
 }
 
-__device__ void house_qr_lds(double* M, int ldm, int mrows, int c, double* red) {
+// One Householder step on column j, taken by every wave on its own copy of
+// the column (RR row registers per lane, mrows - j <= 64 RR).  The wave
+// applies the reflector to columns j + 1 + wave + 4 t, four at a time; the
+// norm of column j and the first four dot products x^T a_l are reduced
+// together, and v^T a_l = x^T a_l - alpha a_jl since v = x - alpha e_j.
+template <int RR>
+__device__ __forceinline__ void house_step(double* M, int ldm, int mrows, int c, int j, int lane, int wave,
+                                           double& alpha, double& vtop, double& tau) {
+  int row[RR];
+  bool in[RR];
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    const int i = j + lane + 64 * r;
+    in[r] = i < mrows;
+    row[r] = in[r] ? i : mrows - 1;   // loads stay in range; masked below
+  }
+  double v[RR];
+  double s = 0.0;
+#pragma unroll
+  for (int r = 0; r < RR; ++r) {
+    const double x = M[row[r] + j * ldm];
+    v[r] = in[r] ? x : 0.0;
+    s += v[r] * v[r];
+  }
+  const int l0 = j + 1 + wave;
+  double y[4][RR];
+  double d[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int l = min(l0 + 4 * t, c - 1);
+    double e = 0.0;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      const double x = M[row[r] + l * ldm];
+      y[t][r] = in[r] ? x : 0.0;
+      e += v[r] * y[t][r];
+    }
+    d[t] = e;
+  }
+  const double nrm = sqrt(wave_sum64(s));
+#pragma unroll
+  for (int t = 0; t < 4; ++t) d[t] = wave_sum64(d[t]);
+  const double a = wave_bcast(v[0], 0);
+  alpha = (a >= 0.0) ? -nrm : nrm;
+  const double vtv = 2.0 * nrm * (nrm + fabs(a));
+  tau = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+  vtop = a - alpha;
+  if (tau == 0.0) return;
+  if (lane == 0) v[0] = vtop;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int l = l0 + 4 * t;
+    if (l < c) {
+      const double sd = (d[t] - alpha * wave_bcast(y[t][0], 0)) * tau;
+#pragma unroll
+      for (int r = 0; r < RR; ++r)
+        if (in[r]) M[row[r] + l * ldm] = y[t][r] - sd * v[r];
+    }
+  }
+  for (int g = l0 + 16; g < c; g += 16) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int l = min(g + 4 * t, c - 1);
+      double e = 0.0;
+#pragma unroll
+      for (int r = 0; r < RR; ++r) {
+        const double x = M[row[r] + l * ldm];
+        y[t][r] = in[r] ? x : 0.0;
+        e += v[r] * y[t][r];
+      }
+      d[t] = e;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) d[t] = wave_sum64(d[t]) * tau;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int l = g + 4 * t;
+      if (l < c) {
+#pragma unroll
+        for (int r = 0; r < RR; ++r)
+          if (in[r]) M[row[r] + l * ldm] = y[t][r] - d[t] * v[r];
+      }
+    }
+  }
+}
+
+// Householder QR of an mrows x c matrix in LDS (col-major, leading dimension
+// ldm), mrows <= 64 RM, RM a power of two.  One barrier per column: each
+// step reads only columns > j, and column j + 1 is final once the step on
+// column j is.  With KEEP the reflector tails stay below the diagonal, with
+// the leading entry in vtop[j] and the scale in beta[j]
+// (H_j = I - beta[j] v_j v_j^T); without it the leading min(c, mrows) rows
+// are cleared below the diagonal, leaving R there.
+template <int RM, bool KEEP>
+__device__ void house_qr_cols(double* M, int ldm, int mrows, int c, double* vtop, double* beta) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = 0; j < c && j < mrows; ++j) {
+  const int jn = min(c, mrows);
+  for (int j = 0; j < jn; ++j) {
+    const int R = (mrows - j + 63) >> 6;
+    double alpha, vt, tau;
+    if (R <= 1)
+      house_step<1>(M, ldm, mrows, c, j, lane, wave, alpha, vt, tau);
+    else if (RM <= 2 || R <= 2)
+      house_step<(RM < 2 ? RM : 2)>(M, ldm, mrows, c, j, lane, wave, alpha, vt, tau);
+    else if (RM <= 4 || R <= 4)
+      house_step<(RM < 4 ? RM : 4)>(M, ldm, mrows, c, j, lane, wave, alpha, vt, tau);
+    else
+      house_step<RM>(M, ldm, mrows, c, j, lane, wave, alpha, vt, tau);
+    __syncthreads();
+    // column j is final; later steps touch only columns > j
     if (wave == 0) {
-      double s = 0.0;
-      for (int i = j + lane; i < mrows; i += 64) {
-        double v = M[i + j * ldm];
-        s += v * v;
-      }
-      s = wave_sum64(s);
-      if (lane == 0) {
-        double nrm = sqrt(s);
-        double a = M[j + j * ldm];
-        double alpha = (a >= 0.0) ? -nrm : nrm;
-        double vtv = 2.0 * nrm * (nrm + fabs(a));   // v = x - alpha e1
-        red[0] = alpha;
-        red[1] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-        M[j + j * ldm] = a - alpha;
+      if (KEEP) {
+        if (lane == 0) {
+          vtop[j] = vt;
+          beta[j] = tau;
+          M[j + j * ldm] = alpha;
+        }
+      } else {
+        if (lane == 0) M[j + j * ldm] = alpha;
+        for (int i = j + 1 + lane; i < jn; i += 64) M[i + j * ldm] = 0.0;
       }
     }
-    __syncthreads();
-    const double beta = red[1];
-    if (beta != 0.0) {
-      // wave w updates columns j + 1 + w + 4 t, four at a time so that their
-      // reductions overlap
-      for (int l0 = j + 1 + wave; l0 < c; l0 += 16) {
-        double sd[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int l = l0 + 4 * t;
-          double s = 0.0;
-          if (l < c)
-            for (int i = j + lane; i < mrows; i += 64) s += M[i + j * ldm] * M[i + l * ldm];
-          sd[t] = s;
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) sd[t] = wave_sum64(sd[t]) * beta;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int l = l0 + 4 * t;
-          if (l < c)
-            for (int i = j + lane; i < mrows; i += 64) M[i + l * ldm] -= sd[t] * M[i + j * ldm];
-        }
-      }
-    }
-    __syncthreads();
-    // column j is final; the next column's steps touch only columns > j
-    if (tid == 0) M[j + j * ldm] = red[0];
-    for (int i = j + 1 + tid; i < mrows; i += 256) M[i + j * ldm] = 0.0;
   }
   __syncthreads();
+}
+
+constexpr int QR_RM = 8;               // row registers per lane in the TSQR QR
+constexpr int QR_ROWS = 64 * QR_RM;    // rows reduced per pass
+
+__device__ void house_qr_lds(double* M, int ldm, int mrows, int c) {
+  house_qr_cols<QR_RM, false>(M, ldm, mrows, c, nullptr, nullptr);
 }
 
 __device__ __forceinline__ int qr_ldm(int c) { return QR_LDS / (c > 0 ? c : 1); }
@@ -459,15 +539,15 @@ __global__ __launch_bounds__(256) void k_tsqr_seg(const Bufs* __restrict__ bufs,
   double* __restrict__ R = refp(bufs, S.R);
   extern __shared__ double smem[];
   double* M = smem;
-  double* red = smem + QR_LDS;
   const int tid = threadIdx.x;
   if (c <= 0) return;
   const int ldm = qr_ldm(c);
+  const int prow = min(ldm, QR_ROWS);
   const double* __restrict__ X = refp(bufs, S.X);
   const int ld = S.X.ld;
   int have = 0;
   for (int base = 0, nr = 0; base < S.rows; base += nr) {
-    nr = min(ldm - have, S.rows - base);
+    nr = min(prow - have, S.rows - base);
     for (int b0 = 0; b0 < nr * c; b0 += 2048) {
       double r[8];
 #pragma unroll
@@ -485,7 +565,7 @@ __global__ __launch_bounds__(256) void k_tsqr_seg(const Bufs* __restrict__ bufs,
     }
     __syncthreads();
     int mrows = have + nr;
-    house_qr_lds(M, ldm, mrows, c, red);
+    house_qr_lds(M, ldm, mrows, c);
     have = min(mrows, c);
   }
   for (int e = tid; e < c * c; e += 256) {
@@ -501,10 +581,10 @@ __global__ __launch_bounds__(256) void k_tsqr_red(const Bufs* __restrict__ bufs,
   double* __restrict__ R = refp(bufs, S.R);
   extern __shared__ double smem[];
   double* M = smem;
-  double* red = smem + QR_LDS;
   const int tid = threadIdx.x;
   if (c <= 0) return;
   const int ldm = qr_ldm(c);
+  const int prow = min(ldm, QR_ROWS);
   const double* __restrict__ R0 = refp(bufs, S.R0);
   const size_t RR = (size_t)rmax * rmax;
   int have = 0;
@@ -513,7 +593,7 @@ __global__ __launch_bounds__(256) void k_tsqr_red(const Bufs* __restrict__ bufs,
     // stack as many segment R factors as fit under the current R
     int mrows = have;
     const int s_start = s;
-    while (s < S.nseg && mrows + c <= ldm) {
+    while (s < S.nseg && mrows + c <= prow) {
       const double* Rs = R0 + RR * s;
       for (int e = tid; e < c * c; e += 256) {
         int i = e % c, l = e / c;
@@ -522,9 +602,9 @@ __global__ __launch_bounds__(256) void k_tsqr_red(const Bufs* __restrict__ bufs,
       mrows += c;
       ++s;
     }
-    if (s == s_start) break;   // cannot happen for c <= 80 (2c <= ldm)
+    if (s == s_start) break;   // cannot happen for c <= 80 (2c <= prow)
     __syncthreads();
-    house_qr_lds(M, ldm, mrows, c, red);
+    house_qr_lds(M, ldm, mrows, c);
     have = min(mrows, c);
   }
   for (int e = tid; e < c * c; e += 256) {
@@ -1148,56 +1228,8 @@ __device__ void sketch_p_inv_reg(const double* T, const int* piv, int n, int kk,
 // reflectors: on exit R is in the upper triangle, v_j below the diagonal of
 // column j with its leading entry in vtop[j], and H_j = I - beta[j] v_j v_j^T,
 // so that M = H_0 H_1 ... H_{n-1} R.
-__device__ void house_qr_keep(double* M, int n, double* vtop, double* beta, double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int j = 0; j < n; ++j) {
-    if (wave == 0) {
-      double sq = 0.0;
-      for (int i = j + lane; i < n; i += 64) sq += M[i + j * SM] * M[i + j * SM];
-      sq = wave_sum64(sq);
-      if (lane == 0) {
-        const double nrm = sqrt(sq);
-        const double a = M[j + j * SM];
-        const double alpha = (a >= 0.0) ? -nrm : nrm;
-        const double vtv = 2.0 * nrm * (nrm + fabs(a));
-        red[0] = alpha;
-        red[1] = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-        M[j + j * SM] = a - alpha;
-      }
-    }
-    __syncthreads();
-    const double b = red[1];
-    if (b != 0.0) {
-      // wave w updates columns j + 1 + w + 4 t, four at a time
-      for (int l0 = j + 1 + wave; l0 < n; l0 += 16) {
-        double sd[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int l = l0 + 4 * t;
-          double sdot = 0.0;
-          if (l < n)
-            for (int i = j + lane; i < n; i += 64) sdot += M[i + j * SM] * M[i + l * SM];
-          sd[t] = sdot;
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) sd[t] = wave_sum64(sd[t]) * b;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          const int l = l0 + 4 * t;
-          if (l < n)
-            for (int i = j + lane; i < n; i += 64) M[i + l * SM] -= sd[t] * M[i + j * SM];
-        }
-      }
-    }
-    __syncthreads();
-    // column j is final; the next column's steps touch only columns > j
-    if (tid == 0) {
-      vtop[j] = M[j + j * SM];
-      beta[j] = b;
-      M[j + j * SM] = red[0];
-    }
-  }
-  __syncthreads();
+__device__ void house_qr_keep(double* M, int n, double* vtop, double* beta) {
+  house_qr_cols<(SM + 63) / 64, true>(M, SM, n, n, vtop, beta);
 }
 
 // Small dense problems built from upper-triangular R factors.
@@ -1340,7 +1372,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
       V[i + j * SM] = A[j + i * SM];
     }
     __syncthreads();
-    house_qr_keep(V, n, sv, beta, red);
+    house_qr_keep(V, n, sv, beta);
     for (int e = tid; e < n * n; e += 256) {
       const int i = e % n, j = e / n;
       if (i > j) R1[j * n - j * (j + 1) / 2 + (i - j - 1)] = V[i + j * SM];
@@ -1459,7 +1491,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
       V[i + j * SM] = A[j + i * SM];
     }
     __syncthreads();
-    house_qr_keep(V, n, vtop, beta, red);
+    house_qr_keep(V, n, vtop, beta);
     // reflectors (strictly lower part) to packed storage, B = R2^T into A
     for (int e = tid; e < n * n; e += 256) {
       int i = e % n, j = e / n;
