@@ -359,11 +359,13 @@ constexpr int QR_CMAX = 96;          // max columns
 
 // Cross-lane moves inside a row of 16 lanes (DPP: a plain vector
 // instruction, no LDS round trip), applied to both halves of a double.
+// Every control used here is a permutation of the 16 lanes of a row, so
+// each lane has a source and no fill value is needed.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
   const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(int(b & 0xffffffffLL), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 constexpr int DPP_XOR1 = 0xB1;          // quad_perm [1,0,3,2]
@@ -388,6 +390,15 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return (wave_bcast(v, 0) + wave_bcast(v, 16)) + (wave_bcast(v, 32) + wave_bcast(v, 48));
 }
 
+// Sum over each row of 16 lanes, the same bits in every lane of the row.
+__device__ __forceinline__ double row_sum16(double v) {
+  v += dpp_move<DPP_MIRROR>(v);
+  v += dpp_move<DPP_HALF_MIRROR>(v);
+  v += dpp_move<DPP_XOR2>(v);
+  v += dpp_move<DPP_XOR1>(v);
+  return v;
+}
+
 // Largest value over the 64 lanes of a wave (NaN ignored), in every lane.
 __device__ __forceinline__ double wave_max64(double v) {
   v = fmax(v, dpp_move<DPP_MIRROR>(v));
@@ -397,114 +408,101 @@ __device__ __forceinline__ double wave_max64(double v) {
   return fmax(fmax(wave_bcast(v, 0), wave_bcast(v, 16)), fmax(wave_bcast(v, 32), wave_bcast(v, 48)));
 }
 
-// One Householder step on column j, taken by every wave on its own copy of
-// the column (RR row registers per lane, mrows - j <= 64 RR).  The wave
-// applies the reflector to columns j + 1 + wave + 4 t, four at a time; the
-// norm of column j and the first four dot products x^T a_l are reduced
-// together, and v^T a_l = x^T a_l - alpha a_jl since v = x - alpha e_j.
-template <int RR>
-__device__ __forceinline__ void house_step(double* M, int ldm, int mrows, int c, int j, int lane, int wave,
-                                           double& alpha, double& vtop, double& tau) {
-  int row[RR];
-  bool in[RR];
-#pragma unroll
-  for (int r = 0; r < RR; ++r) {
-    const int i = j + lane + 64 * r;
-    in[r] = i < mrows;
-    row[r] = in[r] ? i : mrows - 1;   // loads stay in range; masked below
-  }
-  double v[RR];
-  double s = 0.0;
-#pragma unroll
-  for (int r = 0; r < RR; ++r) {
-    const double x = M[row[r] + j * ldm];
-    v[r] = in[r] ? x : 0.0;
-    s += v[r] * v[r];
-  }
-  const int l0 = j + 1 + wave;
-  double y[4][RR];
-  double d[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int l = min(l0 + 4 * t, c - 1);
-    double e = 0.0;
-#pragma unroll
-    for (int r = 0; r < RR; ++r) {
-      const double x = M[row[r] + l * ldm];
-      y[t][r] = in[r] ? x : 0.0;
-      e += v[r] * y[t][r];
-    }
-    d[t] = e;
-  }
-  const double nrm = sqrt(wave_sum64(s));
-#pragma unroll
-  for (int t = 0; t < 4; ++t) d[t] = wave_sum64(d[t]);
-  const double a = wave_bcast(v[0], 0);
-  alpha = (a >= 0.0) ? -nrm : nrm;
-  const double vtv = 2.0 * nrm * (nrm + fabs(a));
-  tau = (vtv > 0.0) ? 2.0 / vtv : 0.0;
-  vtop = a - alpha;
-  if (tau == 0.0) return;
-  if (lane == 0) v[0] = vtop;
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int l = l0 + 4 * t;
-    if (l < c) {
-      const double sd = (d[t] - alpha * wave_bcast(y[t][0], 0)) * tau;
-#pragma unroll
-      for (int r = 0; r < RR; ++r)
-        if (in[r]) M[row[r] + l * ldm] = y[t][r] - sd * v[r];
-    }
-  }
-  for (int g = l0 + 16; g < c; g += 16) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int l = min(g + 4 * t, c - 1);
-      double e = 0.0;
-#pragma unroll
-      for (int r = 0; r < RR; ++r) {
-        const double x = M[row[r] + l * ldm];
-        y[t][r] = in[r] ? x : 0.0;
-        e += v[r] * y[t][r];
-      }
-      d[t] = e;
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) d[t] = wave_sum64(d[t]) * tau;
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int l = g + 4 * t;
-      if (l < c) {
-#pragma unroll
-        for (int r = 0; r < RR; ++r)
-          if (in[r]) M[row[r] + l * ldm] = y[t][r] - d[t] * v[r];
-      }
-    }
-  }
-}
-
 // Householder QR of an mrows x c matrix in LDS (col-major, leading dimension
-// ldm), mrows <= 64 RM, RM a power of two.  One barrier per column: each
-// step reads only columns > j, and column j + 1 is final once the step on
-// column j is.  With KEEP the reflector tails stay below the diagonal, with
-// the leading entry in vtop[j] and the scale in beta[j]
-// (H_j = I - beta[j] v_j v_j^T); without it the leading min(c, mrows) rows
-// are cleared below the diagonal, leaving R there.
-template <int RM, bool KEEP>
-__device__ void house_qr_cols(double* M, int ldm, int mrows, int c, double* vtop, double* beta) {
+// ldm >= 16 RR >= mrows; rows mrows .. 16 RR - 1 of every column are zero on
+// entry and stay zero).  Lane 16 t + q of a wave holds rows q + 16 r of one
+// column, so a row of 16 lanes reduces a dot product over the column with
+// four DPP moves and a wave treats four columns at once: wave w applies the
+// reflector of column j to columns j + 1 + 4 w + 16 g + t.  In registers the
+// reflector keeps only the rows below j; row j enters through the element
+// a_jl read by every lane (v^T a_l = sum_{i>j} x_i a_il + (x_j - alpha) a_jl)
+// and is written by one lane.  One barrier per column: a step reads only
+// columns >= j, and column j + 1 is final once the step on column j is.
+// With KEEP the reflector tails stay below the diagonal, with the leading
+// entry in vtop[j] and the scale in beta[j] (H_j = I - beta[j] v_j v_j^T);
+// without it the leading min(c, mrows) rows are cleared below the diagonal,
+// leaving R there.
+template <int RR, bool KEEP>
+__device__ void house_qr_rr(double* M, int ldm, int mrows, int c, double* vtop, double* beta) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = lane & 15, t = lane >> 4;
   const int jn = min(c, mrows);
   for (int j = 0; j < jn; ++j) {
-    const int R = (mrows - j + 63) >> 6;
-    double alpha, vt, tau;
-    if (R <= 1)
-      house_step<1>(M, ldm, mrows, c, j, lane, wave, alpha, vt, tau);
-    else if (RM <= 2 || R <= 2)
-      house_step<(RM < 2 ? RM : 2)>(M, ldm, mrows, c, j, lane, wave, alpha, vt, tau);
-    else if (RM <= 4 || R <= 4)
-      house_step<(RM < 4 ? RM : 4)>(M, ldm, mrows, c, j, lane, wave, alpha, vt, tau);
-    else
-      house_step<RM>(M, ldm, mrows, c, j, lane, wave, alpha, vt, tau);
+    const double* cj = M + q + j * ldm;
+    double v[RR];
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      const double x = cj[16 * r];
+      v[r] = (q + 16 * r > j) ? x : 0.0;
+      if (r & 1) s1 += v[r] * v[r];
+      else s0 += v[r] * v[r];
+    }
+    const double xj = M[j + j * ldm];
+    const int g0 = j + 1 + 4 * wave;
+    const int lA = g0 + t, lB = lA + 16;
+    const bool two = g0 + 16 < c;   // uniform: a second group of columns
+    double* cA = M + min(lA, c - 1) * ldm;
+    double* cB = M + min(lB, c - 1) * ldm;
+    double yA[RR], yB[RR];
+    double dA0 = 0.0, dA1 = 0.0, dB0 = 0.0, dB1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < RR; ++r) {
+      yA[r] = cA[q + 16 * r];
+      if (r & 1) dA1 += v[r] * yA[r];
+      else dA0 += v[r] * yA[r];
+    }
+    const double eA = cA[j];
+    double eB = 0.0;
+    if (two) {
+#pragma unroll
+      for (int r = 0; r < RR; ++r) {
+        yB[r] = cB[q + 16 * r];
+        if (r & 1) dB1 += v[r] * yB[r];
+        else dB0 += v[r] * yB[r];
+      }
+      eB = cB[j];
+    }
+    const double sq = row_sum16(s0 + s1);
+    const double dA = row_sum16(dA0 + dA1);
+    const double dB = two ? row_sum16(dB0 + dB1) : 0.0;
+    const double nrm = sqrt(sq + xj * xj);
+    const double alpha = (xj >= 0.0) ? -nrm : nrm;
+    const double vtv = 2.0 * nrm * (nrm + fabs(xj));   // v = x - alpha e_j
+    const double tau = (vtv > 0.0) ? 2.0 / vtv : 0.0;
+    const double vt = xj - alpha;
+    if (tau != 0.0) {
+      if (lA < c) {
+        const double sd = (dA + vt * eA) * tau;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) cA[q + 16 * r] = yA[r] - sd * v[r];
+        if (q == 0) cA[j] = eA - sd * vt;
+      }
+      if (two && lB < c) {
+        const double sd = (dB + vt * eB) * tau;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) cB[q + 16 * r] = yB[r] - sd * v[r];
+        if (q == 0) cB[j] = eB - sd * vt;
+      }
+      for (int g = g0 + 32; g < c; g += 16) {
+        const int l = g + t;
+        double* cl = M + min(l, c - 1) * ldm;
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < RR; ++r) {
+          yA[r] = cl[q + 16 * r];
+          if (r & 1) d1 += v[r] * yA[r];
+          else d0 += v[r] * yA[r];
+        }
+        const double e = cl[j];
+        const double sd = (row_sum16(d0 + d1) + vt * e) * tau;
+        if (l < c) {
+#pragma unroll
+          for (int r = 0; r < RR; ++r) cl[q + 16 * r] = yA[r] - sd * v[r];
+          if (q == 0) cl[j] = e - sd * vt;
+        }
+      }
+    }
     __syncthreads();
     // column j is final; later steps touch only columns > j
     if (wave == 0) {
@@ -523,14 +521,37 @@ __device__ void house_qr_cols(double* M, int ldm, int mrows, int c, double* vtop
   __syncthreads();
 }
 
-constexpr int QR_RM = 8;               // row registers per lane in the TSQR QR
-constexpr int QR_ROWS = 64 * QR_RM;    // rows reduced per pass
-
-__device__ void house_qr_lds(double* M, int ldm, int mrows, int c) {
-  house_qr_cols<QR_RM, false>(M, ldm, mrows, c, nullptr, nullptr);
+// house_qr_rr for rr = ceil(mrows / 16) blocks of rows, 1 <= rr <= RR
+template <int RR, bool KEEP>
+__device__ __forceinline__ void house_qr_blocks(int rr, double* M, int ldm, int mrows, int c, double* vtop,
+                                                double* beta) {
+  if constexpr (RR <= 1) {
+    house_qr_rr<1, KEEP>(M, ldm, mrows, c, vtop, beta);
+  } else {
+    if (rr >= RR) house_qr_rr<RR, KEEP>(M, ldm, mrows, c, vtop, beta);
+    else house_qr_blocks<RR - 1, KEEP>(rr, M, ldm, mrows, c, vtop, beta);
+  }
 }
 
-__device__ __forceinline__ int qr_ldm(int c) { return QR_LDS / (c > 0 ? c : 1); }
+// Zero rows mrows .. 16 ceil(mrows / 16) - 1 of columns 0 .. c-1 (the padding
+// the 16-row blocks of house_qr_rr read); the caller synchronises.
+__device__ __forceinline__ void qr_zero_pad(double* M, int ldm, int mrows, int c) {
+  const int pad = ((mrows + 15) & ~15) - mrows;
+  for (int e = threadIdx.x; e < pad * c; e += blockDim.x) M[mrows + e % pad + (e / pad) * ldm] = 0.0;
+}
+
+constexpr int QR_RM = 24;              // row registers per lane in the TSQR QR
+constexpr int QR_ROWS = 16 * QR_RM;    // rows reduced per pass
+
+// R of the mrows x c matrix in LDS (mrows <= QR_ROWS, ldm a multiple of 16
+// and >= mrows): pads the last block of rows with zeros, then factors.
+__device__ __forceinline__ void house_qr_lds(double* M, int ldm, int mrows, int c) {
+  qr_zero_pad(M, ldm, mrows, c);
+  __syncthreads();
+  house_qr_blocks<QR_RM, false>((mrows + 15) >> 4, M, ldm, mrows, c, nullptr, nullptr);
+}
+
+__device__ __forceinline__ int qr_ldm(int c) { return (QR_LDS / (c > 0 ? c : 1)) & ~15; }
 
 __global__ __launch_bounds__(256) void k_tsqr_seg(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
                                                   const TsqrSeg* __restrict__ segs, int s0, int rmax) {
@@ -1229,7 +1250,9 @@ __device__ void sketch_p_inv_reg(const double* T, const int* piv, int n, int kk,
 // column j with its leading entry in vtop[j], and H_j = I - beta[j] v_j v_j^T,
 // so that M = H_0 H_1 ... H_{n-1} R.
 __device__ void house_qr_keep(double* M, int n, double* vtop, double* beta) {
-  house_qr_cols<(SM + 63) / 64, true>(M, SM, n, n, vtop, beta);
+  qr_zero_pad(M, SM, n, n);
+  __syncthreads();
+  house_qr_blocks<SM / 16, true>((n + 15) >> 4, M, SM, n, n, vtop, beta);
 }
 
 // Small dense problems built from upper-triangular R factors.
