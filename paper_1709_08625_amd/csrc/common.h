@@ -29,6 +29,21 @@ __device__ __forceinline__ double* refp(const Bufs* __restrict__ b, const Ref& r
   return b->p[r.buf] + r.off;
 }
 
+// A pointer read from memory is generic to the compiler, and its loads
+// become flat loads, which also count against the LDS wait counter: a wait
+// for an LDS read then waits for every global load in flight.  Every buffer
+// here is device memory; accesses through gmem(p) are global loads and
+// stores.
+#define HC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const HC_GLOBAL T* gmem(const T* p) {
+  return (const HC_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ HC_GLOBAL T* gmem(T* p) {
+  return (HC_GLOBAL T*)p;
+}
+
 __device__ __forceinline__ int dimv(const int* __restrict__ dyn, const Dim& d) {
   if (d.slot < 0) return d.maxv;
   int v = dyn[d.slot] + d.add;

@@ -37,6 +37,22 @@ constexpr int GR = GK * GT / 256;   // elements of each operand chunk per thread
 // pointers, leading dimensions, live dimensions and the intersection with
 // the tile.  This replaces the per-product chain of dependent loads
 // (descriptor -> dynamic dimensions -> buffer table -> data).
+// Values known to be equal in every lane, moved to scalar registers.
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform_dbl(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane(int(b & 0xffffffffLL));
+  const int hi = __builtin_amdgcn_readfirstlane(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long u = reinterpret_cast<unsigned long long>(p);
+  const unsigned lo = __builtin_amdgcn_readfirstlane(unsigned(u & 0xffffffffull));
+  const unsigned hi = __builtin_amdgcn_readfirstlane(unsigned(u >> 32));
+  return reinterpret_cast<T*>((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
 constexpr int PBATCH = 32;
 struct ProdMeta {
   const double* A;
@@ -60,47 +76,76 @@ __device__ __forceinline__ void gemm_products(const Bufs* __restrict__ bufs, con
                                               ProdMeta* pm, AddF on_add, ChunkF on_chunk) {
   const int tid = threadIdx.x;
   // element e of a chunk: A chunk is GT x GK, B chunk GK x GT; the index
-  // split follows the operand's storage order so that lanes coalesce
-  T ra[GR], rb[GR];
+  // split follows the operand's storage order so that lanes coalesce.  The
+  // loads of the next chunk stay in flight while the current one is used:
+  // they read a valid element of the product even outside its extent (bit r
+  // of ma / mb records which are real), and the mask and scale are applied
+  // only when the chunk goes to LDS.  Descriptor fields are the same in
+  // every lane: scalar registers, so that the operand layout is one uniform
+  // branch and the loads take a scalar base address.
+  double ra[GR], rb[GR];
+  unsigned ma = 0, mb = 0;
   auto fetch = [&](const ProdMeta& M, int k0) {
+    const HC_GLOBAL double* __restrict__ MA = gmem(uniform_ptr(M.A));
+    const HC_GLOBAL double* __restrict__ MB = gmem(uniform_ptr(M.B));
+    const int ta = uniform_int(M.ta), tb = uniform_int(M.tb);
+    const int lda = uniform_int(M.lda), ldb = uniform_int(M.ldb), kp = uniform_int(M.k);
+    const int pr0 = uniform_int(M.pr0), pr1 = uniform_int(M.pr1);
+    const int pc0 = uniform_int(M.pc0), pc1 = uniform_int(M.pc1);
+    ma = 0;
+    mb = 0;
+    if (ta == 0) {
 #pragma unroll
-    for (int r = 0; r < GR; ++r) {
-      int e = tid + 256 * r;
-      int ii = M.ta == 0 ? (e & (GT - 1)) : (e / GK);
-      int kk = M.ta == 0 ? (e / GT) : (e & (GK - 1));
-      int gi = r0 + ii, gk = k0 + kk;
-      double v = 0.0;
-      if (gi >= M.pr0 && gi < M.pr1 && gk < M.k) {
-        int li = gi - M.pr0;
-        v = M.ta == 0 ? M.A[li + (size_t)gk * M.lda] : M.A[gk + (size_t)li * M.lda];
+      for (int r = 0; r < GR; ++r) {
+        const int e = tid + 256 * r;
+        const int gi = r0 + (e & (GT - 1)), gk = k0 + e / GT;
+        const bool ok = gi >= pr0 && gi < pr1 && gk < kp;
+        ra[r] = MA[(ok ? gi - pr0 : 0) + (size_t)(ok ? gk : 0) * lda];
+        ma |= unsigned(ok) << r;
       }
-      ra[r] = T(M.alpha * v);
+    } else {
+#pragma unroll
+      for (int r = 0; r < GR; ++r) {
+        const int e = tid + 256 * r;
+        const int gi = r0 + e / GK, gk = k0 + (e & (GK - 1));
+        const bool ok = gi >= pr0 && gi < pr1 && gk < kp;
+        ra[r] = MA[(ok ? gk : 0) + (size_t)(ok ? gi - pr0 : 0) * lda];
+        ma |= unsigned(ok) << r;
+      }
     }
+    if (tb == 0) {
 #pragma unroll
-    for (int r = 0; r < GR; ++r) {
-      int e = tid + 256 * r;
-      int kk = M.tb == 0 ? (e & (GK - 1)) : (e / GT);
-      int jj = M.tb == 0 ? (e / GK) : (e & (GT - 1));
-      int gj = c0 + jj, gk = k0 + kk;
-      double v = 0.0;
-      if (gj >= M.pc0 && gj < M.pc1 && gk < M.k) {
-        int lj = gj - M.pc0;
-        v = M.tb == 0 ? M.B[gk + (size_t)lj * M.ldb] : M.B[lj + (size_t)gk * M.ldb];
+      for (int r = 0; r < GR; ++r) {
+        const int e = tid + 256 * r;
+        const int gk = k0 + (e & (GK - 1)), gj = c0 + e / GK;
+        const bool ok = gj >= pc0 && gj < pc1 && gk < kp;
+        rb[r] = MB[(ok ? gk : 0) + (size_t)(ok ? gj - pc0 : 0) * ldb];
+        mb |= unsigned(ok) << r;
       }
-      rb[r] = T(v);
+    } else {
+#pragma unroll
+      for (int r = 0; r < GR; ++r) {
+        const int e = tid + 256 * r;
+        const int gk = k0 + e / GT, gj = c0 + (e & (GT - 1));
+        const bool ok = gj >= pc0 && gj < pc1 && gk < kp;
+        rb[r] = MB[(ok ? gj - pc0 : 0) + (size_t)(ok ? gk : 0) * ldb];
+        mb |= unsigned(ok) << r;
+      }
     }
   };
   const ProdMeta* pmc = pm;
-  auto stash = [&](int ta, int tb) {
+  auto stash = [&](const ProdMeta& M) {
+    const int ta = uniform_int(M.ta), tb = uniform_int(M.tb);
+    const double alpha = uniform_dbl(M.alpha);
 #pragma unroll
     for (int r = 0; r < GR; ++r) {
       int e = tid + 256 * r;
       int ii = ta == 0 ? (e & (GT - 1)) : (e / GK);
       int kk = ta == 0 ? (e / GT) : (e & (GK - 1));
-      As[kk][ii] = ra[r];
+      As[kk][ii] = T(((ma >> r) & 1u) ? alpha * ra[r] : 0.0);
       int k2 = tb == 0 ? (e & (GK - 1)) : (e / GT);
       int jj = tb == 0 ? (e / GK) : (e & (GT - 1));
-      Bs[k2][jj] = rb[r];
+      Bs[k2][jj] = T(((mb >> r) & 1u) ? rb[r] : 0.0);
     }
   };
 
@@ -143,7 +188,7 @@ __device__ __forceinline__ void gemm_products(const Bufs* __restrict__ bufs, con
     fetch(pmc[q], 0);
     while (q < cnt) {
       if (k0 > 0 || q > 0) __syncthreads();   // LDS tiles of the previous pair consumed
-      stash(pmc[q].ta, pmc[q].tb);
+      stash(pmc[q]);
       __syncthreads();
       int nq = q, nk0 = k0 + GK;
       if (nk0 >= pmc[q].k) {
@@ -178,7 +223,7 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
       for (int y = 0; y < NY; ++y) {
         int gi = r0 + ty + 16 * x, gj = c0 + tx + 16 * y;
         if (gi >= M.pr0 && gi < M.pr1 && gj >= M.pc0 && gj < M.pc1)
-          acc[x][y] += T(M.alpha * M.A[(gi - M.pr0) + (size_t)(gj - M.pc0) * M.lda]);
+          acc[x][y] += T(M.alpha * gmem(M.A)[(gi - M.pr0) + (size_t)(gj - M.pc0) * M.lda]);
       }
   };
   auto on_chunk = [&](int kl) {
@@ -196,7 +241,7 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
     }
   };
   gemm_products<T>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm, on_add, on_chunk);
-  double* __restrict__ C = refp(bufs, J.C);
+  HC_GLOBAL double* __restrict__ C = gmem(refp(bufs, J.C));
   const int ldc = J.C.ld;
 #pragma unroll
   for (int x = 0; x < NX; ++x) {
@@ -224,7 +269,7 @@ __device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, co
                                                const GemmJob& J, const GemmProd* __restrict__ prods, int m,
                                                int n, int r0, int c0, double (*As)[GT + 1], double (*Bs)[GT + 1],
                                                ProdMeta* pm) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = uniform_int(tid >> 6), lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int er = min(GT, m - r0), ec = min(GT, n - c0);
   const int nbr = (er + 15) >> 4, nbc = (ec + 15) >> 4, nblk = nbr * nbc;
@@ -261,7 +306,7 @@ __device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, co
         for (int r = 0; r < 4; ++r) {
           const int gj = c0 + 16 * bj[t] + 4 * r + lk;
           if (gi >= M.pr0 && gi < M.pr1 && gj >= M.pc0 && gj < M.pc1)
-            acc[t][r] += M.alpha * M.A[(gi - M.pr0) + (size_t)(gj - M.pc0) * M.lda];
+            acc[t][r] += M.alpha * gmem(M.A)[(gi - M.pr0) + (size_t)(gj - M.pc0) * M.lda];
         }
       }
     }
@@ -298,7 +343,7 @@ __device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, co
     }
   }
   if (kpart != 0) return;
-  double* __restrict__ C = refp(bufs, J.C);
+  HC_GLOBAL double* __restrict__ C = gmem(refp(bufs, J.C));
   const int ldc = J.C.ld;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
