@@ -1191,6 +1191,99 @@ __device__ int qrcp_wave(double* T, int n, double tau, int* piv, int* kout) {
   return k;
 }
 
+// Single-wave column-pivoted QR for n <= RU, with the contract of qrcp_wave
+// (same pivot rule, stopping rule and output).  A lane keeps its column in
+// registers with the row of the current step at index 0: after each step
+// the registers shift down by one, so every register index is static.  The
+// pivot column goes through xs (RU doubles of LDS) as a broadcast, and each
+// row of T is stored as it becomes final.
+template <int RU>
+__device__ int qrcp_reg(double* T, int n, double tau, int* piv, int* kout, double* xs) {
+  const int lane = threadIdx.x;   // called by the first wave only
+  bool active = lane < n;
+  double col[RU];
+#pragma unroll
+  for (int u = 0; u < RU; ++u) {
+    const double v = T[u * TLD + (active ? lane : 0)];
+    col[u] = (active && u < n) ? v : 0.0;
+  }
+  double cn = 0.0;
+#pragma unroll
+  for (int u = 0; u < RU; ++u) cn = fma(col[u], col[u], cn);
+  double cn0 = cn;
+  double r0 = 0.0;
+  int k = n;
+  for (int j = 0; j < n; ++j) {
+    // pivot: the largest remaining norm, ties to the lowest column
+    const double bv = active ? cn : -1.0;
+    const double mx = wave_max64(bv);
+    const unsigned long long hit = __ballot(active && bv == mx);
+    if (hit == 0ull) {   // only NaN norms remain
+      k = j;
+      break;
+    }
+    const int p = __ffsll((long long)hit) - 1;
+    if (lane == p) {
+#pragma unroll
+      for (int u = 0; u < RU; ++u) xs[u] = col[u];
+    }
+    wave_sync_lds();
+    double x[RU];
+#pragma unroll
+    for (int u = 0; u < RU; ++u) x[u] = xs[u];
+    // exact norm of the pivot column from row j on (four partial sums)
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < RU; ++u) q[u & 3] = fma(x[u], x[u], q[u & 3]);
+    const double nrm = sqrt((q[0] + q[1]) + (q[2] + q[3]));
+    if (j == 0) r0 = nrm;
+    if (!(nrm > tau * r0) || !(nrm > 0.0)) {
+      k = j;
+      break;
+    }
+    const double a = x[0];
+    const double alpha = (a >= 0.0) ? -nrm : nrm;
+    const double beta = 2.0 / (2.0 * nrm * (nrm + fabs(a)));
+    const double vj = a - alpha;
+    if (lane == p) {
+      active = false;
+      T[j * TLD + p] = alpha;
+    }
+    if (active) {
+      double w[4] = {vj * col[0], 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int u = 1; u < RU; ++u) w[(u - 1) & 3] = fma(x[u], col[u], w[(u - 1) & 3]);
+      const double ws = ((w[0] + w[1]) + (w[2] + w[3])) * beta;
+      col[0] -= ws * vj;
+#pragma unroll
+      for (int u = 1; u < RU; ++u) col[u] -= ws * x[u];
+      T[j * TLD + lane] = col[0];
+      const double r = col[0];
+      double c = cn - r * r;
+      if (!(c > 1e-8 * cn0)) {
+        c = 0.0;
+#pragma unroll
+        for (int u = 1; u < RU; ++u) c = fma(col[u], col[u], c);
+        cn0 = c;
+      }
+      cn = c;
+    }
+    if (lane == 0) piv[j] = p;
+    // row j + 1 to register 0
+#pragma unroll
+    for (int u = 0; u + 1 < RU; ++u) col[u] = col[u + 1];
+    col[RU - 1] = 0.0;
+    wave_sync_lds();   // xs is rewritten by the next step
+  }
+  // the columns never chosen follow in increasing order, so that piv[0..n)
+  // is a permutation (their rows of the result are zero)
+  const unsigned long long rest = __ballot(active);
+  if (active) piv[k + __popcll(rest & ((1ull << lane) - 1ull))] = lane;
+  if (lane == 0) *kout = k;
+  wave_sync_lds();
+  return k;
+}
+
 // Lane-private vectors of RU doubles with compile-time register indices:
 // an element at a run-time index is read or written by a select over all of
 // them (no dynamic register indexing).
@@ -1341,7 +1434,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     }
     __syncthreads();
     if (tid < 64) {
-      const int kk = qrcp_wave(V, n, eps, ord, &s_kr);
+      const int kk = qrcp_reg<32>(V, n, eps, ord, &s_kr, sv);
       sketch_p_inv_reg<32>(V, ord, n, kk, C1, rmax);
     }
     if (tid == 0) dyn[J.out_rank_slot] = s_kr;
