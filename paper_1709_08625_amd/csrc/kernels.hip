@@ -1300,59 +1300,68 @@ __device__ __forceinline__ void reg_set(double (&r)[RU], int j, double x) {
   for (int u = 0; u < RU; ++u) r[u] = (u == j) ? x : r[u];
 }
 
-// Second half for n <= RU: lane c < kk forms Z = Q2 V[:, ord[c]] in
-// registers (reflectors applied last to first, each read as a broadcast),
-// then C1[:, c] = R2^{-1} Z[:, c] by column-oriented back substitution.
-template <int RU>
-__device__ void sketch_f_out_reg(const double* V, const double* R1, const double* R2, const double* beta,
-                                 const int* ord, int n, int kk, double* __restrict__ C1, int rmax) {
-  const int c = threadIdx.x;
+// Second half for n <= 32 by the work-group: eight lanes per output column
+// c < kk, lane s holding rows s + 8 r (r < 4).  Z = Q2 V[:, ord[c]]
+// (reflectors applied last to first, each read as a broadcast, each dot
+// product reduced over the eight lanes with DPP moves), then
+// C1[:, c] = R2^{-1} Z[:, c] by back substitution, each new entry passed
+// along the eight lanes of its column by a lane permute.
+__device__ void sketch_f_out_wg(const double* V, const double* R1, const double* R2, const double* beta,
+                                const int* ord, int n, int kk, double* __restrict__ C1, int rmax) {
+  const int tid = threadIdx.x, c = tid >> 3, s = tid & 7, lane = tid & 63;
   const bool act = c < kk;
   const int oc = act ? ord[c] : 0;
-  double z[RU];
+  double z[4];
 #pragma unroll
-  for (int u = 0; u < RU; ++u) {
+  for (int r = 0; r < 4; ++r) {
+    const int u = s + 8 * r;
     const double x = V[u + oc * SM];
-    z[u] = (act && u < n) ? x : 0.0;
+    z[r] = (act && u < n) ? x : 0.0;
   }
   for (int j = n - 1; j >= 0; --j) {
     const double bj = beta[j];
     if (bj == 0.0) continue;
     const double v0 = beta[SM + j];
-    const int base = j * n - j * (j + 1) / 2 - j - 1;
-    double cv[RU];
+    const int base = j * n - j * (j + 1) / 2 - j - 1;   // packed reflector tail, rows > j
+    double cv[4];
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      const double r = R1[u > j ? base + u : 0];
-      cv[u] = (u == j) ? v0 : ((u > j && u < n) ? r : 0.0);
+    for (int r = 0; r < 4; ++r) {
+      const int u = s + 8 * r;
+      const bool tail = u > j && u < n;
+      const double t = R1[tail ? base + u : 0];
+      cv[r] = (u == j) ? v0 : (tail ? t : 0.0);
     }
-    double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+    double d = cv[0] * z[0];
+    d = fma(cv[1], z[1], d);
+    d = fma(cv[2], z[2], d);
+    d = fma(cv[3], z[3], d);
+    d = group_sum<8>(d) * bj;
 #pragma unroll
-    for (int u = 0; u < RU; ++u) {
-      if (u % 4 == 0) d0 = fma(cv[u], z[u], d0);
-      if (u % 4 == 1) d1 = fma(cv[u], z[u], d1);
-      if (u % 4 == 2) d2 = fma(cv[u], z[u], d2);
-      if (u % 4 == 3) d3 = fma(cv[u], z[u], d3);
-    }
-    const double d = ((d0 + d1) + (d2 + d3)) * bj;
-#pragma unroll
-    for (int u = 0; u < RU; ++u) z[u] = fma(-d, cv[u], z[u]);
+    for (int r = 0; r < 4; ++r) z[r] = fma(-d, cv[r], z[r]);
   }
+  for (int i = n - 1; i >= 0; --i) {
+    const double* col = R2 + i * (i + 1) / 2;   // packed upper column i
+    const double dg = col[i];
+    const int si = i & 7, ri = i >> 3;
+    double zi = z[0];
+    if (ri == 1) zi = z[1];
+    if (ri == 2) zi = z[2];
+    if (ri == 3) zi = z[3];
+    double x = (dg != 0.0) ? zi / dg : 0.0;   // right on the lane holding row i
+    x = __shfl(x, (lane & ~7) | si);
 #pragma unroll
-  for (int i = RU - 1; i >= 0; --i) {
-    if (i < n) {
-      const double* col = R2 + i * (i + 1) / 2;
-      const double d = col[i];
-      const double x = (d != 0.0) ? z[i] / d : 0.0;
-      z[i] = x;
-#pragma unroll
-      for (int u = 0; u < i; ++u) z[u] = fma(-col[u], x, z[u]);
+    for (int r = 0; r < 4; ++r) {
+      const int u = s + 8 * r;
+      const double cu = col[u < i ? u : 0];
+      z[r] = (u == i) ? x : ((u < i) ? fma(-cu, x, z[r]) : z[r]);
     }
   }
   if (act) {
 #pragma unroll
-    for (int u = 0; u < RU; ++u)
-      if (u < n) C1[u + (size_t)c * rmax] = z[u];
+    for (int r = 0; r < 4; ++r) {
+      const int u = s + 8 * r;
+      if (u < n) C1[u + (size_t)c * rmax] = z[r];
+    }
   }
 }
 
@@ -1584,9 +1593,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
         kk = J.cap;
       }
       if (J.sat.maxv >= 0 && kk >= dimv(dyn, J.sat) && lane == 0) atomicOr(status, STAT_SKETCH_SAT);
-      if (n <= 32) {
-        sketch_f_out_reg<32>(V, R1, R2, beta, ord, n, kk, C1, rmax);
-      } else {
+      if (n > 32) {
         // Z = Q2 V[:, ord[c]] (lane c, row i at A[i * TLD + c]); A is free now
         const int c = lane;
         if (c < kk)
@@ -1618,6 +1625,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
       if (lane == 0) s_kk = kk;
     }
     __syncthreads();
+    if (n <= 32) sketch_f_out_wg(V, R1, R2, beta, ord, n, s_kk, C1, rmax);
     if (tid == 0) dyn[J.out_rank_slot] = s_kk;
     return;
   }
