@@ -85,67 +85,81 @@ __device__ __forceinline__ void gemm_products(const Bufs* __restrict__ bufs, con
   // branch and the loads take a scalar base address.
   double ra[GR], rb[GR];
   unsigned ma = 0, mb = 0;
+  // element r of a thread: with the operand's leading index contiguous
+  // (ta == 0 / tb == 1) the thread keeps index tid % 64 and takes k steps of
+  // 4 (k = tid / 64 + 4 r); with k contiguous it keeps k = tid % 32 and takes
+  // index steps of 8 (tid / 32 + 8 r).  Either way element r sits at a
+  // fixed per-thread byte offset plus r times a uniform stride (32-bit: the
+  // planner keeps every operand below 2^29 elements), and a range check is
+  // one unsigned compare.
+  auto fetch_op = [&](const HC_GLOBAL char* base, int lead_major, int ld, int lo, int hi, int g0, int kp,
+                      int k0, double* dst) -> unsigned {
+    unsigned m = 0;
+    if (lead_major) {
+      const int gi = g0 + (tid & (GT - 1));
+      const bool iok = unsigned(gi - lo) < unsigned(hi - lo);
+      const int kb = k0 + (tid >> 6);
+      const unsigned off0 = (unsigned(iok ? gi - lo : 0) + unsigned(kb) * unsigned(ld)) * 8u;
+      const unsigned step = 32u * unsigned(ld);
+#pragma unroll
+      for (int r = 0; r < GR; ++r) {
+        const bool ok = iok && kb + 4 * r < kp;
+        const unsigned off = ok ? off0 + unsigned(r) * step : 0u;
+        dst[r] = *(const HC_GLOBAL double*)(base + off);
+        m |= unsigned(ok) << r;
+      }
+    } else {
+      const int gk = k0 + (tid & (GK - 1));
+      const bool kok = gk < kp;
+      const int ib = g0 + (tid >> 5) - lo;
+      const unsigned off0 = (unsigned(gk) + unsigned(ib) * unsigned(ld)) * 8u;
+      const unsigned step = 64u * unsigned(ld);
+#pragma unroll
+      for (int r = 0; r < GR; ++r) {
+        const bool ok = kok && unsigned(ib + 8 * r) < unsigned(hi - lo);
+        const unsigned off = ok ? off0 + unsigned(r) * step : 0u;
+        dst[r] = *(const HC_GLOBAL double*)(base + off);
+        m |= unsigned(ok) << r;
+      }
+    }
+    return m;
+  };
   auto fetch = [&](const ProdMeta& M, int k0) {
-    const HC_GLOBAL double* __restrict__ MA = gmem(uniform_ptr(M.A));
-    const HC_GLOBAL double* __restrict__ MB = gmem(uniform_ptr(M.B));
-    const int ta = uniform_int(M.ta), tb = uniform_int(M.tb);
-    const int lda = uniform_int(M.lda), ldb = uniform_int(M.ldb), kp = uniform_int(M.k);
-    const int pr0 = uniform_int(M.pr0), pr1 = uniform_int(M.pr1);
-    const int pc0 = uniform_int(M.pc0), pc1 = uniform_int(M.pc1);
-    ma = 0;
-    mb = 0;
-    if (ta == 0) {
-#pragma unroll
-      for (int r = 0; r < GR; ++r) {
-        const int e = tid + 256 * r;
-        const int gi = r0 + (e & (GT - 1)), gk = k0 + e / GT;
-        const bool ok = gi >= pr0 && gi < pr1 && gk < kp;
-        ra[r] = MA[(ok ? gi - pr0 : 0) + (size_t)(ok ? gk : 0) * lda];
-        ma |= unsigned(ok) << r;
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < GR; ++r) {
-        const int e = tid + 256 * r;
-        const int gi = r0 + e / GK, gk = k0 + (e & (GK - 1));
-        const bool ok = gi >= pr0 && gi < pr1 && gk < kp;
-        ra[r] = MA[(ok ? gk : 0) + (size_t)(ok ? gi - pr0 : 0) * lda];
-        ma |= unsigned(ok) << r;
-      }
-    }
-    if (tb == 0) {
-#pragma unroll
-      for (int r = 0; r < GR; ++r) {
-        const int e = tid + 256 * r;
-        const int gk = k0 + (e & (GK - 1)), gj = c0 + e / GK;
-        const bool ok = gj >= pc0 && gj < pc1 && gk < kp;
-        rb[r] = MB[(ok ? gk : 0) + (size_t)(ok ? gj - pc0 : 0) * ldb];
-        mb |= unsigned(ok) << r;
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < GR; ++r) {
-        const int e = tid + 256 * r;
-        const int gk = k0 + e / GT, gj = c0 + (e & (GT - 1));
-        const bool ok = gj >= pc0 && gj < pc1 && gk < kp;
-        rb[r] = MB[(ok ? gj - pc0 : 0) + (size_t)(ok ? gk : 0) * ldb];
-        mb |= unsigned(ok) << r;
-      }
-    }
+    // descriptor fields are the same in every lane: scalar registers, so
+    // that the operand layout is one uniform branch and the loads take a
+    // scalar base address
+    const HC_GLOBAL char* MA = (const HC_GLOBAL char*)gmem(uniform_ptr(M.A));
+    const HC_GLOBAL char* MB = (const HC_GLOBAL char*)gmem(uniform_ptr(M.B));
+    const int kp = uniform_int(M.k);
+    ma = fetch_op(MA, uniform_int(M.ta) == 0, uniform_int(M.lda), uniform_int(M.pr0), uniform_int(M.pr1), r0, kp,
+                  k0, ra);
+    mb = fetch_op(MB, uniform_int(M.tb) == 1, uniform_int(M.ldb), uniform_int(M.pc0), uniform_int(M.pc1), c0, kp,
+                  k0, rb);
   };
   const ProdMeta* pmc = pm;
   auto stash = [&](const ProdMeta& M) {
     const int ta = uniform_int(M.ta), tb = uniform_int(M.tb);
     const double alpha = uniform_dbl(M.alpha);
+    T* __restrict__ Af = &As[0][0];
+    T* __restrict__ Bf = &Bs[0][0];
+    // element r of the leading-index-contiguous layout lands at
+    // [tid / 64 + 4 r][tid % 64], of the k-contiguous one at
+    // [tid % 32][tid / 32 + 8 r]: a per-thread base and an immediate offset
+    const int lead0 = (tid >> 6) * (GT + 1) + (tid & (GT - 1));
+    const int kmaj0 = (tid & (GK - 1)) * (GT + 1) + (tid >> 5);
+    if (ta == 0) {
 #pragma unroll
-    for (int r = 0; r < GR; ++r) {
-      int e = tid + 256 * r;
-      int ii = ta == 0 ? (e & (GT - 1)) : (e / GK);
-      int kk = ta == 0 ? (e / GT) : (e & (GK - 1));
-      As[kk][ii] = T(((ma >> r) & 1u) ? alpha * ra[r] : 0.0);
-      int k2 = tb == 0 ? (e & (GK - 1)) : (e / GT);
-      int jj = tb == 0 ? (e / GK) : (e & (GT - 1));
-      Bs[k2][jj] = T(((mb >> r) & 1u) ? rb[r] : 0.0);
+      for (int r = 0; r < GR; ++r) Af[lead0 + 4 * r * (GT + 1)] = T(((ma >> r) & 1u) ? alpha * ra[r] : 0.0);
+    } else {
+#pragma unroll
+      for (int r = 0; r < GR; ++r) Af[kmaj0 + 8 * r] = T(((ma >> r) & 1u) ? alpha * ra[r] : 0.0);
+    }
+    if (tb == 1) {
+#pragma unroll
+      for (int r = 0; r < GR; ++r) Bf[lead0 + 4 * r * (GT + 1)] = T(((mb >> r) & 1u) ? rb[r] : 0.0);
+    } else {
+#pragma unroll
+      for (int r = 0; r < GR; ++r) Bf[kmaj0 + 8 * r] = T(((mb >> r) & 1u) ? rb[r] : 0.0);
     }
   };
 
@@ -172,15 +186,20 @@ __device__ __forceinline__ void gemm_products(const Bufs* __restrict__ bufs, con
       pm[tid] = M;
     }
     __syncthreads();
-    // element-wise additions of partial sums (tb == 2)
-    for (int q = 0; q < cnt; ++q) {
-      const ProdMeta& M = pmc[q];
-      if (M.live && M.tb == 2) on_add(M);
+    // live products and live element-wise additions of partial sums
+    // (tb == 2) of the batch as bit masks, the same in every wave
+    bool is_prod = false, is_add = false;
+    if ((tid & 63) < cnt) {
+      const ProdMeta& M = pmc[tid & 63];
+      is_prod = M.live && M.tb != 2;
+      is_add = M.live && M.tb == 2;
     }
+    const unsigned long long prod_mask = __ballot(is_prod), add_mask = __ballot(is_add);
+    for (unsigned long long am = add_mask; am != 0ull; am &= am - 1ull) on_add(pmc[__ffsll((long long)am) - 1]);
     // products: (product, k-chunk) pairs in order
     auto next_live = [&](int q) {
-      while (q < cnt && (!pmc[q].live || pmc[q].tb == 2)) ++q;
-      return q;
+      const unsigned long long rest = q < 64 ? prod_mask & (~0ull << q) : 0ull;
+      return rest != 0ull ? __ffsll((long long)rest) - 1 : cnt;
     };
     int q = next_live(0);
     if (q >= cnt) continue;

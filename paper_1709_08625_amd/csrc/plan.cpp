@@ -1310,6 +1310,15 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
   Bd.build_solves();
   Bd.build_matvec();
   if (Bd.dyn_max > P.n_dyn) P.n_dyn = Bd.dyn_max;
+  // the GEMM kernel addresses an element of a product operand by a 32-bit
+  // byte offset from the operand's start
+  for (const GemmProd& g : P.gprods) {
+    if (g.tb == 2) continue;
+    const int64_t kk = g.k.maxv, mi = g.mi.maxv, nj = g.nj.maxv;
+    const int64_t a = g.ta == 0 ? mi + kk * g.A.ld : kk + mi * g.A.ld;
+    const int64_t b = g.tb == 0 ? kk + nj * g.B.ld : nj + kk * g.B.ld;
+    if (std::max(a, b) >= (int64_t(1) << 29)) return "a GEMM operand spans 2^29 elements or more";
+  }
   int64_t launches = 0;
   for (auto& s : P.steps)
     for (auto& x : s) launches += (x.kind != ST_FORK && x.kind != ST_JOIN) ? 1 : 0;
