@@ -880,15 +880,15 @@ __device__ void jacobi_wg_rounds(double* A, double* V, int n, double thr2) {
         double* __restrict__ Aq = A + qq * SM;
         double* __restrict__ Vp = V + pp * SM;
         double* __restrict__ Vq = V + qq * SM;
+        // rows n .. G RU - 1 are zero (padded by jacobi_wg) and stay zero
         double xr[RU], yr[RU], vx[RU], vy[RU];
 #pragma unroll
         for (int u = 0; u < RU; ++u) {
           const int i = gl + G * u;
-          const bool in = i < n;
-          xr[u] = in ? Ap[i] : 0.0;
-          yr[u] = in ? Aq[i] : 0.0;
-          vx[u] = in ? Vp[i] : 0.0;
-          vy[u] = in ? Vq[i] : 0.0;
+          xr[u] = Ap[i];
+          yr[u] = Aq[i];
+          vx[u] = Vp[i];
+          vy[u] = Vq[i];
         }
         double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -909,12 +909,10 @@ __device__ void jacobi_wg_rounds(double* A, double* V, int n, double thr2) {
 #pragma unroll
             for (int u = 0; u < RU; ++u) {
               const int i = gl + G * u;
-              if (i < n) {
-                Ap[i] = cs * xr[u] - sn * yr[u];
-                Aq[i] = sn * xr[u] + cs * yr[u];
-                Vp[i] = cs * vx[u] - sn * vy[u];
-                Vq[i] = sn * vx[u] + cs * vy[u];
-              }
+              Ap[i] = cs * xr[u] - sn * yr[u];
+              Aq[i] = sn * xr[u] + cs * yr[u];
+              Vp[i] = cs * vx[u] - sn * vy[u];
+              Vq[i] = sn * vx[u] + cs * vy[u];
             }
           }
         }
@@ -933,13 +931,28 @@ __device__ void jacobi_wg_rounds(double* A, double* V, int n, double thr2) {
   }
 }
 
+// Zero rows n .. rows - 1 of the first n columns of A and V (ld SM).
+__device__ __forceinline__ void jacobi_zero_pad(double* A, double* V, int n, int rows) {
+  const int pad = rows - n;
+  for (int e = threadIdx.x; e < pad * n; e += 256) {
+    const int i = n + e % pad, j = e / pad;
+    A[i + j * SM] = 0.0;
+    V[i + j * SM] = 0.0;
+  }
+  __syncthreads();
+}
+
 __device__ void jacobi_wg(double* A, double* V, int n, double thr2) {
-  if (n <= 16)
+  if (n <= 16) {
+    jacobi_zero_pad(A, V, n, 16);
     jacobi_wg_rounds<16, 1>(A, V, n, thr2);
-  else if (n <= 32)
+  } else if (n <= 32) {
+    jacobi_zero_pad(A, V, n, 32);
     jacobi_wg_rounds<16, 2>(A, V, n, thr2);
-  else
+  } else {
+    jacobi_zero_pad(A, V, n, 64);
     jacobi_wg_rounds<8, 8>(A, V, n, thr2);
+  }
 }
 
 // Work-group Jacobi for n <= 64 with V := identity first.
