@@ -1540,12 +1540,42 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     return;
   }
   if (J.kind == SK_SKETCH_F && n <= 64) {
-    // The truncation: the first wave (lane = row) forms M = R1 R2^{-1}; the
+    // The truncation: eight lanes per row (n <= 32; else the first wave,
+    // lane = row) form M = R1 R2^{-1}; the
     // work-group forms M^T = Q2 R2' (Householder, reflectors kept) and runs
     // one-sided Jacobi on B = R2'^T with V; the first wave forms
     // Z = Q2 V[:, ord] and C1 = R2^{-1} Z_k.
     __shared__ int s_kk;
-    if (tid < 64) {
+    if (n <= 32) {
+      // M row by row with eight lanes per row i (tid / 8), lane s holding
+      // the entries l = s + 8 r: entry j is the row's dot product so far with
+      // column j of R2 (reduced over the eight lanes by DPP), subtracted
+      // from R1's entry and divided by the diagonal
+      const int i = tid >> 3, s = tid & 7;
+      double g[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < n; ++j) {
+        const double* col = R2 + j * (j + 1) / 2;   // column j of R2 (rows <= j)
+        double p = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int l = s + 8 * r;
+          const double c = col[l < j ? l : 0];
+          p = fma(l < j ? g[r] : 0.0, c, p);
+        }
+        p = group_sum<8>(p);
+        const double a = (i < n && i <= j) ? R1[upk(i, j)] : 0.0;
+        const double d = col[j];
+        const double gj = (d != 0.0) ? (a - p) / d : 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (j == s + 8 * r) g[r] = gj;
+      }
+      if (i < n) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (s + 8 * r < n) A[i + (s + 8 * r) * SM] = g[r];
+      }
+    } else if (tid < 64) {
       const int lane = tid;
       // M column by column (col-major in A); a lane reads only its own row
       // (four partial sums per entry)
