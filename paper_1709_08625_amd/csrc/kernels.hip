@@ -380,7 +380,10 @@ __device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, co
   }
 }
 
-__global__ __launch_bounds__(256) void k_gemm(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
+// Four work-groups per CU (at most 128 registers a lane): the LDS chunks
+// fit four times, and the fourth work-group hides more of each tile's
+// operand-load latency than the registers it costs.
+__global__ __launch_bounds__(256, 4) void k_gemm(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
                                               const GemmJob* __restrict__ jobs,
                                               const GemmProd* __restrict__ prods,
                                               const GemmTile* __restrict__ tiles, int t0) {
