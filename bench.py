@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--n", type=int, default=512000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--profile-kind", default="gemm")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch the sweep stage by stage instead of replaying captured graph segments")
     ap.add_argument("--workload", default="loglik512k", choices=["loglik512k", "serving", "fit128k"])
     ap.add_argument("--evals", type=int, default=30)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
@@ -195,6 +197,8 @@ def main():
     stream = torch.cuda.current_stream().cuda_stream
     t_build = time.perf_counter()
     opts = {"precision": hcov.MIXED if args.precision == "mixed" else hcov.FP64}
+    if args.no_graphs:
+        opts["use_graphs"] = 0
     H = hcov.HCov(locs, theta0, eps=eps, leaf=leaf, eta=eta, stream=stream, opts=opts)
     t_build = time.perf_counter() - t_build
     progress(f"trees, plan and first assembly at n={n}: {t_build:.1f} s")
