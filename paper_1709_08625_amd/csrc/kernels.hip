@@ -1400,30 +1400,37 @@ __device__ void sketch_f_out_wg(const double* V, const double* R1, const double*
   }
 }
 
-// C1 = Pi R'_k^{-1} for n <= RU by the first wave: lane c < k forms column c
-// of R'_k^{-1} in registers by column-oriented substitution from e_c (every
-// lane walks the same columns, so R' is read as a broadcast), then writes
-// row piv[i] of C1 for every i < n (zero for i > c).
-template <int RU>
-__device__ void sketch_p_inv_reg(const double* T, const int* piv, int n, int kk, double* __restrict__ C1, int rmax) {
-  const int c = threadIdx.x;
-  double x[RU];
+// C1 = Pi R'_k^{-1} for n <= 32 by the work-group: eight lanes per column
+// c < k (tid / 8), lane s holding rows s + 8 r; column c of R'_k^{-1} by
+// column-oriented substitution from e_c (R' read as a broadcast), each new
+// entry passed along the column's lanes by a lane permute; then row piv[u]
+// of C1 for every u < n (zero for u > c).
+__device__ void sketch_p_inv_wg(const double* T, const int* piv, int n, int kk, double* __restrict__ C1,
+                                int rmax) {
+  const int tid = threadIdx.x, c = tid >> 3, s = tid & 7, lane = tid & 63;
+  double x[4];
 #pragma unroll
-  for (int u = 0; u < RU; ++u) x[u] = (u == c) ? 1.0 : 0.0;
+  for (int r = 0; r < 4; ++r) x[r] = (s + 8 * r == c) ? 1.0 : 0.0;
 #pragma unroll
-  for (int l = RU - 1; l >= 0; --l) {
+  for (int l = 31; l >= 0; --l) {
     if (l < kk) {
       const int pl = piv[l];
-      const double xl = x[l] / T[l * TLD + pl];
-      x[l] = xl;
+      double xl = x[l >> 3] / T[l * TLD + pl];   // right on the lane holding row l
+      xl = __shfl(xl, (lane & ~7) | (l & 7));
 #pragma unroll
-      for (int u = 0; u < l; ++u) x[u] = fma(-T[u * TLD + pl], xl, x[u]);
+      for (int r = 0; r < 4; ++r) {
+        const int u = s + 8 * r;
+        const double t = T[(u < l ? u : 0) * TLD + pl];
+        x[r] = (u == l) ? xl : ((u < l) ? fma(-t, xl, x[r]) : x[r]);
+      }
     }
   }
   if (c < kk) {
 #pragma unroll
-    for (int u = 0; u < RU; ++u)
-      if (u < n) C1[piv[u] + (size_t)c * rmax] = (u <= c) ? x[u] : 0.0;
+    for (int r = 0; r < 4; ++r) {
+      const int u = s + 8 * r;
+      if (u < n) C1[piv[u] + (size_t)c * rmax] = (u <= c) ? x[r] : 0.0;
+    }
   }
 }
 
@@ -1469,18 +1476,17 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
   if (J.kind != SK_SKETCH_P) load_upper(refp(bufs, J.R2), rmax, n, R2);
   __syncthreads();
   if (J.kind == SK_SKETCH_P && n <= 32) {
-    // pivoted QR on R1 transposed into V (row i at V[i * TLD]), then the
-    // inverse with the columns in registers, both by the first wave
+    // pivoted QR on R1 transposed into V (row i at V[i * TLD]) by the first
+    // wave, then the inverse by the work-group
     __shared__ int s_kr;
     for (int e = tid; e < n * n; e += 256) {
       int i = e / n, l = e % n;
       V[i * TLD + l] = (i <= l) ? R1[upk(i, l)] : 0.0;
     }
     __syncthreads();
-    if (tid < 64) {
-      const int kk = qrcp_reg<32>(V, n, eps, ord, &s_kr, sv);
-      sketch_p_inv_reg<32>(V, ord, n, kk, C1, rmax);
-    }
+    if (tid < 64) qrcp_reg<32>(V, n, eps, ord, &s_kr, sv);
+    __syncthreads();
+    sketch_p_inv_wg(V, ord, n, s_kr, C1, rmax);
     if (tid == 0) dyn[J.out_rank_slot] = s_kr;
     return;
   }
