@@ -1353,9 +1353,10 @@ __device__ void sketch_f_out_wg(const double* V, const double* R1, const double*
     const double x = V[u + oc * SM];
     z[r] = (act && u < n) ? x : 0.0;
   }
-  for (int j = n - 1; j >= 0; --j) {
+#pragma unroll
+  for (int j = 31; j >= 0; --j) {
+    if (j >= n) continue;
     const double bj = beta[j];
-    if (bj == 0.0) continue;
     const double v0 = beta[SM + j];
     const int base = j * n - j * (j + 1) / 2 - j - 1;   // packed reflector tail, rows > j
     double cv[4];
@@ -1372,18 +1373,15 @@ __device__ void sketch_f_out_wg(const double* V, const double* R1, const double*
     d = fma(cv[3], z[3], d);
     d = group_sum<8>(d) * bj;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) z[r] = fma(-d, cv[r], z[r]);
+    for (int r = 0; r < 4; ++r) z[r] = (bj != 0.0) ? fma(-d, cv[r], z[r]) : z[r];   // bj == 0: H_j = I
   }
-  for (int i = n - 1; i >= 0; --i) {
+#pragma unroll
+  for (int i = 31; i >= 0; --i) {
+    if (i >= n) continue;
     const double* col = R2 + i * (i + 1) / 2;   // packed upper column i
     const double dg = col[i];
-    const int si = i & 7, ri = i >> 3;
-    double zi = z[0];
-    if (ri == 1) zi = z[1];
-    if (ri == 2) zi = z[2];
-    if (ri == 3) zi = z[3];
-    double x = (dg != 0.0) ? zi / dg : 0.0;   // right on the lane holding row i
-    x = __shfl(x, (lane & ~7) | si);
+    double x = (dg != 0.0) ? z[i >> 3] / dg : 0.0;   // right on the lane holding row i
+    x = __shfl(x, (lane & ~7) | (i & 7));
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int u = s + 8 * r;
