@@ -86,7 +86,19 @@ typedef struct {
                              HIP graph on a stream of the context and replayed
                              by later factorisations (default 1); 0: every
                              stage is launched separately */
+  int oversample;         /* columns of a low-rank target's randomised sketch
+                             in the factorisation's recompression beyond its
+                             rank estimate (the larger of the block's assembled
+                             rank and the rank its factor block kept in the
+                             context's last factorisation); default 10, range
+                             [2, 64]; the width is capped at max_rank + 16 and
+                             at min(rows, cols) of the block */
+  int on_saturation;      /* HCOV_SAT_RETRY (default) or HCOV_SAT_ERROR: what a
+                             saturated sketch does, see hcov_cholesky */
 } hcov_opts;
+
+#define HCOV_SAT_RETRY 0
+#define HCOV_SAT_ERROR 1
 
 /* Structure and work counters of a context (see hcov_stats). */
 typedef struct {
@@ -105,6 +117,9 @@ typedef struct {
   int64_t n_steps;            /* sweep steps of the factorisation (= 2^D) */
   int64_t n_launches_factor;  /* kernel launches of one factorisation */
   int64_t n_graph_replays;    /* factorisations run as a replay of the captured sweep */
+  int64_t n_sketch_retries;   /* factorisations redone with wider sketches */
+  int sketch_saturated;       /* saturated sketches in the last factorisation */
+  double mean_sketch_width;   /* mean sketch width of the low-rank blocks */
 } hcov_stats_t;
 
 typedef struct hcov_ctx hcov_ctx;
@@ -147,8 +162,24 @@ int hcov_build(const double* locs_xy, int64_t n, hcov_theta theta, double eps,
 int hcov_set_theta(hcov_ctx* ctx, hcov_theta theta);
 
 /* H-Cholesky C~ = L~ L~^T in place [HLIBCov Eq. (2), Sec. 2.2: H-matrix
- * factorisation with the same fixed accuracy eps for the factor].  Returns
- * HCOV_ENOTSPD if a diagonal leaf has a non-positive or non-finite pivot. */
+ * factorisation with the same fixed accuracy eps for the factor].
+ *
+ * Returns HCOV_ENOTSPD if a diagonal leaf has a non-finite pivot or a pivot
+ * that does not exceed 64 p u times its diagonal entry (leaf order p,
+ * u = 2^-53): Sec. 3 notes that nearly dependent columns (coincident
+ * locations) break the factorisation and that a nugget (Sec. 5.2) cures it.
+ *
+ * Every updated low-rank block is recompressed to accuracy eps from a
+ * randomised sketch (width: see opts.oversample).  When a block keeps a rank
+ * of at least the width minus one while the sketch is narrower than the
+ * block, the sketch is saturated and eps is no longer guaranteed for that
+ * block; its rank hint is then doubled.  With HCOV_SAT_RETRY the matrix is
+ * re-assembled and the factorisation redone with the wider sketches, up to 4
+ * times; a sketch saturated at the widest width (max_rank + 16), saturation
+ * after the last retry, or any saturation with HCOV_SAT_ERROR returns
+ * HCOV_ERANK.  The factorisation is never reported as done (HCOV_OK) with a
+ * saturated sketch.  Rank hints persist in the context, so later
+ * factorisations (new theta) start from the ranks the last one needed. */
 int hcov_cholesky(hcov_ctx* ctx);
 
 /* log|C~| = 2 sum_i log L~_ii [HLIBCov Eq. (2)], FP64 reduction in a fixed

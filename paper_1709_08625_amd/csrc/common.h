@@ -14,12 +14,14 @@ struct Bufs {
 };
 
 // Status bits written by kernels (device int status[0]); status[1] holds the
-// first failing cluster-order row of a non-SPD pivot (atomicMin).
+// first failing cluster-order row of a non-SPD pivot (atomicMin), status[2]
+// the number of saturated sketches.
 enum StatusBits : int {
   STAT_RANK_OVERFLOW = 1,   // a block needed more than the rank capacity
   STAT_SKETCH_SAT = 2,      // a randomised sketch showed no decay
   STAT_NOT_SPD = 4,         // non-positive / non-finite pivot
   STAT_NONFINITE = 8,       // non-finite matrix entry
+  STAT_SAT_CAP = 16,        // a sketch saturated at the widest width the plan allows
 };
 
 // The buffer table lives in device memory (one per context): a uniform

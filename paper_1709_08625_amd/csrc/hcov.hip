@@ -67,6 +67,8 @@ struct hcov_ctx {
   std::vector<hipGraphExec_t> gexec[2];   // segments of whole steps, replayed in order
   bool graph_failed = false;
   int64_t n_replays = 0;
+  int64_t n_retries = 0;       // factorisations redone with wider sketches
+  int sat_last = 0;            // saturated sketches of the last factorisation
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   std::vector<Stage> prof_stages;
   // state
@@ -220,11 +222,14 @@ inline int dyn_value(const std::vector<int>& dyn, const Dim& d) {
 double stage_flops(const Plan& P, const std::vector<int>& dyn, const Stage& s) {
   double f = 0.0;
   if (s.kind == ST_GEMM) {
-    int last = -1;
-    for (int t = s.begin; t < s.end; ++t) {
-      int j = P.gtiles[t].job;
-      if (j == last) continue;
-      last = j;
+    // the tiles of a launch are sorted by cost, so one job's tiles need not
+    // be adjacent: count every job of the launch once
+    std::vector<int> jobs;
+    jobs.reserve(size_t(s.end - s.begin));
+    for (int t = s.begin; t < s.end; ++t) jobs.push_back(P.gtiles[t].job);
+    std::sort(jobs.begin(), jobs.end());
+    jobs.erase(std::unique(jobs.begin(), jobs.end()), jobs.end());
+    for (int j : jobs) {
       const GemmJob& J = P.gjobs[j];
       int m = dyn_value(dyn, J.m), n = dyn_value(dyn, J.n);
       for (int q = J.p0; q < J.p1; ++q) {
@@ -247,10 +252,26 @@ double stage_flops(const Plan& P, const std::vector<int>& dyn, const Stage& s) {
   return f;
 }
 
+// Internal (positive) result of a factorisation whose sketches saturated
+// below the widest width: the saturated blocks' rank hints were doubled, and
+// the caller re-assembles and factorises again with the wider sketches.
+constexpr int SAT_RETRY = 1;
+constexpr int MAX_SKETCH_RETRIES = 4;
+
 int check_status(hcov_ctx* c, bool spd_matters) {
-  int st[2];
-  HIPCHK(c, hipMemcpyAsync(st, c->d_status, 8, hipMemcpyDeviceToHost, c->stream));
+  int st[3];
+  HIPCHK(c, hipMemcpyAsync(st, c->d_status, 12, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (spd_matters) c->sat_last = st[2];
+  if (spd_matters && (st[0] & STAT_SKETCH_SAT)) {
+    // a saturated sketch may also have spoiled a later pivot: the retry (or
+    // the error) comes first
+    c->factored = false;
+    if (st[0] & STAT_SAT_CAP)
+      return fail(c, HCOV_ERANK, "a low-rank block's randomised sketch saturated at the widest width (max_rank + 16)");
+    if (c->opts.on_saturation == HCOV_SAT_RETRY) return SAT_RETRY;
+    return fail(c, HCOV_ERANK, "a low-rank block's randomised sketch saturated (on_saturation = HCOV_SAT_ERROR)");
+  }
   if (spd_matters && (st[0] & STAT_NOT_SPD)) {
     c->factored = false;
     return fail(c, HCOV_ENOTSPD, "non-positive pivot at cluster-order row " + std::to_string(st[1]));
@@ -261,8 +282,8 @@ int check_status(hcov_ctx* c, bool spd_matters) {
 }
 
 int reset_status(hcov_ctx* c) {
-  int init[2] = {0, 0x7fffffff};
-  HIPCHK(c, hipMemcpyAsync(c->d_status, init, 8, hipMemcpyHostToDevice, c->stream));
+  static const int init[3] = {0, 0x7fffffff, 0};
+  HIPCHK(c, hipMemcpyAsync(c->d_status, init, 12, hipMemcpyHostToDevice, c->stream));
   return HCOV_OK;
 }
 
@@ -383,6 +404,32 @@ int factor(hcov_ctx* c, const double* z_dev_cluster, bool fuse) {
   return HCOV_OK;
 }
 
+int to_cluster(hcov_ctx* c, const double* z, int where, double* dst);
+
+// Assembly (if needed) and factorisation; with `z` the forward solve of z is
+// fused into the sweep.  A saturated sketch re-assembles C~ and factorises
+// again with the saturated blocks' sketches widened (at most
+// MAX_SKETCH_RETRIES times).
+int factorise(hcov_ctx* c, const double* z, int where) {
+  for (int attempt = 0;; ++attempt) {
+    int r;
+    if (!c->assembled) {
+      r = assemble(c);
+      if (r) return r;
+    }
+    if (z) {
+      r = to_cluster(c, z, where, c->d_buf[B_RHS]);
+      if (r) return r;
+    }
+    r = factor(c, nullptr, z != nullptr);
+    if (r != SAT_RETRY) return r;
+    if (attempt >= MAX_SKETCH_RETRIES)
+      return fail(c, HCOV_ERANK, "sketches still saturated after " + std::to_string(MAX_SKETCH_RETRIES) +
+                                     " retries with doubled widths");
+    c->n_retries += 1;
+  }
+}
+
 int to_cluster(hcov_ctx* c, const double* z, int where, double* dst) {
   if (where == HCOV_HOST) {
     HIPCHK(c, hipMemcpyAsync(c->d_tmp, z, c->n * 8, hipMemcpyHostToDevice, c->stream));
@@ -424,6 +471,8 @@ void hcov_opts_default(hcov_opts* o) {
   o->aca_eps_factor = 0.1;
   o->fuse_solve = 1;
   o->use_graphs = 1;
+  o->oversample = 10;
+  o->on_saturation = HCOV_SAT_RETRY;
 }
 
 const char* hcov_strerror(int code) {
@@ -445,6 +494,8 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   if (opts) o = *opts;
   if (o.max_rank < 1 || o.max_rank > 64 || !(o.aca_eps_factor > 0) || o.aca_eps_factor > 1) return HCOV_EINVAL;
   if (o.precision != HCOV_FP64 && o.precision != HCOV_MIXED) return HCOV_EINVAL;
+  if (o.oversample < 2 || o.oversample > 64) return HCOV_EINVAL;
+  if (o.on_saturation != HCOV_SAT_RETRY && o.on_saturation != HCOV_SAT_ERROR) return HCOV_EINVAL;
   std::vector<double> h(2 * n);
   for (int64_t i = 0; i < 2 * n; ++i) {
     if (!std::isfinite(locs[i])) return HCOV_EINVAL;
@@ -541,7 +592,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   }
   // plan
   int64_t nb = int64_t(c->blocks_lac.size() / 4);
-  e = build_plan(c->plan, n, c->D, leaf, c->blocks_lac.data(), nb, o.max_rank, 10, o.precision == HCOV_MIXED);
+  e = build_plan(c->plan, n, c->D, leaf, c->blocks_lac.data(), nb, o.max_rank, o.precision == HCOV_MIXED);
   if (!e.empty()) {
     c->err = e;
     return bail(HCOV_EINVAL);
@@ -578,13 +629,13 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   // job arrays
   std::vector<FillJob> fj;
   std::vector<AcaJob> aj;
-  std::vector<int2> cp;
+  std::vector<int4> cp;
   for (auto& B : P.blocks) {
     if (B.kind == 0) {
       fj.push_back(FillJob{B.off_d, B.r0, B.c0, int32_t(B.r1 - B.r0), int32_t(B.c1 - B.c0), B.a == B.c ? 1 : 0, 0});
     } else {
       aj.push_back(AcaJob{B.off_u, B.off_v, B.r0, B.c0, int32_t(B.r1 - B.r0), int32_t(B.c1 - B.c0), B.rank0_slot, 0});
-      cp.push_back(make_int2(B.rank_slot, B.rank0_slot));
+      cp.push_back(make_int4(B.rank_slot, B.rank0_slot, B.hint_slot, 0));
     }
   }
   // blocks with more than ACA_BIG_SPLIT rows + columns: multi-work-group ACA
@@ -646,6 +697,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   L.copy_pairs = upload(c, cp);
   L.n_copy = int(cp.size());
   L.rmax = P.rmax;
+  L.oversample = o.oversample;
   L.eps = eps;
   L.tau = std::min(1e-10, 1e-2 * eps);
   L.logdet = c->d_logdet;
@@ -676,11 +728,7 @@ int hcov_set_theta(hcov_ctx* c, hcov_theta theta) {
 int hcov_cholesky(hcov_ctx* c) {
   if (!c) return HCOV_EINVAL;
   if (c->factored) return HCOV_OK;
-  if (!c->assembled) {
-    int r = assemble(c);
-    if (r) return r;
-  }
-  return factor(c, nullptr, false);
+  return factorise(c, nullptr, HCOV_HOST);
 }
 
 int hcov_logdet(hcov_ctx* c, double* out) {
@@ -762,19 +810,13 @@ int hcov_loglik(hcov_ctx* c, const double* z, int where, double* out_ll, double*
   int r;
   double quad = 0, ld = 0;
   if (!c->factored) {
-    if (!c->assembled) {
-      r = assemble(c);
-      if (r) return r;
-    }
     if (c->opts.fuse_solve) {
-      r = to_cluster(c, z, where, c->d_buf[B_RHS]);
-      if (r) return r;
-      r = factor(c, nullptr, true);
+      r = factorise(c, z, where);
       if (r) return r;
       r = reduce_dev(c, c->d_buf[B_RHS], c->n, 0, &quad);
       if (r) return r;
     } else {
-      r = factor(c, nullptr, false);
+      r = factorise(c, nullptr, where);
       if (r) return r;
       r = hcov_forward(c, z, nullptr, &quad, where);
       if (r) return r;
@@ -811,6 +853,8 @@ int hcov_stats(const hcov_ctx* c, hcov_stats_t* s) {
   s->n_steps = int64_t(1) << c->D;
   s->n_launches_factor = P.n_launch_fact;
   s->n_graph_replays = c->n_replays;
+  s->n_sketch_retries = c->n_retries;
+  s->sketch_saturated = c->sat_last;
   // ranks
   std::vector<int> dyn(P.n_dyn + 1);
   if (hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
@@ -827,6 +871,14 @@ int hcov_stats(const hcov_ctx* c, hcov_stats_t* s) {
     fb += double(k) * double((B.r1 - B.r0) + (B.c1 - B.c0));
   }
   s->max_rank_seen = int(mx);
+  {
+    // sketch width of every low-rank block in the last factorisation
+    double w = 0.0;
+    for (auto& B : P.blocks)
+      if (B.kind == 1)
+        w += double(std::min<int64_t>({int64_t(dyn[B.rank0_slot]), B.r1 - B.r0, B.c1 - B.c0, int64_t(P.rcap)}));
+    s->mean_sketch_width = P.n_lr ? w / double(P.n_lr) : 0.0;
+  }
   s->mean_rank = P.n_lr ? double(sum) / double(P.n_lr) : 0.0;
   s->bytes_factor = int64_t(fb * 8.0);
   (void)rows;

@@ -1442,6 +1442,33 @@ __device__ void house_qr_keep(double* M, int n, double* vtop, double* beta) {
   house_qr_blocks<SM / 16, true>((n + 15) >> 4, M, SM, n, n, vtop, beta);
 }
 
+// A randomised sketch Y = M Omega of width r yields a near-optimal basis of
+// the kept rank k only while at least two of its directions are discarded
+// (the expected error of the range finder is bounded by the tail singular
+// values once the oversampling is >= 2).  A kept rank of r - 1 or more with
+// r below min(p, q) therefore means the sketch may have missed part of M's
+// column space at accuracy eps; a sketch of width min(p, q) spans it.
+__device__ __forceinline__ bool sketch_saturated(int kept, int r, int full) {
+  return r < full && kept + 1 >= r;
+}
+
+// Truncation result of a sketched low-rank target (one thread): the kept rank
+// becomes the block's rank hint for the sketch width of the next
+// factorisation; a saturated sketch doubles the hint and raises
+// STAT_SKETCH_SAT (and STAT_SAT_CAP when the sketch was already as wide as
+// the plan allows).
+__device__ __forceinline__ void sketch_report(const SmallJob& J, int* __restrict__ dyn, int kept,
+                                              int* __restrict__ status) {
+  if (J.sat.maxv < 0) return;
+  const int r = dimv(dyn, J.sat);
+  const bool sat = sketch_saturated(kept, r, J.full);
+  if (J.hint_slot >= 0) dyn[J.hint_slot] = sat ? 2 * r : kept;
+  if (sat) {
+    atomicOr(status, r >= J.sat.maxv ? (STAT_SKETCH_SAT | STAT_SAT_CAP) : STAT_SKETCH_SAT);
+    atomicAdd(status + 2, 1);   // saturated blocks of this factorisation
+  }
+}
+
 // Small dense problems built from upper-triangular R factors.
 //   SK_RECOMP   SVD of A = R1 R2^T = X S Y^T (one-sided Jacobi on A):
 //               CU = R2^T Y_k, CV = R1^T X_k S_k^{-1}, k = #{s > eps s_1}
@@ -1661,7 +1688,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
         if (lane == 0) atomicOr(status, STAT_RANK_OVERFLOW);
         kk = J.cap;
       }
-      if (J.sat.maxv >= 0 && kk >= dimv(dyn, J.sat) && lane == 0) atomicOr(status, STAT_SKETCH_SAT);
+      if (lane == 0) sketch_report(J, dyn, kk, status);
       if (n > 32) {
         // Z = Q2 V[:, ord[c]] (lane c, row i at A[i * TLD + c]); A is free now
         const int c = lane;
@@ -1760,10 +1787,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     if (tid == 0) atomicOr(status, STAT_RANK_OVERFLOW);
     kk = J.cap;
   }
-  if (J.kind == SK_SKETCH_F && J.sat.maxv >= 0) {
-    int sat = dimv(dyn, J.sat);
-    if (kk >= sat && tid == 0) atomicOr(status, STAT_SKETCH_SAT);
-  }
+  if (J.kind == SK_SKETCH_F && tid == 0) sketch_report(J, dyn, kk, status);
   if (J.kind == SK_RECOMP) {
     // A V = X S: CU = R2^T Y_k, CV = R1^T X_k S_k^{-1} = R1^T A[:,ord] / s^2
     double* __restrict__ C2 = refp(bufs, J.C2);
@@ -1830,7 +1854,15 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
 // tx + 16b).  Blocked right-looking Cholesky: each 16-column panel is copied
 // to LDS, factorised there column by column, copied back, and applied to the
 // trailing columns from registers.
+//
+// A pivot counts as zero, and the leaf as not positive definite, when it does
+// not exceed 64 p u times the diagonal entry of the updated tile (u = 2^-53):
+// the rounding error of a leaf Cholesky is of order p u |a_jj|, so an exactly
+// singular leaf (two coincident locations without a nugget: two equal
+// columns) gives a pivot of that size and either sign, while a positive
+// definite one stays far above it.
 constexpr int LF = 128, LPW = 16, LPLD = LPW + 1;
+constexpr double PIVOT_REL = 64.0 * 0x1p-53;
 
 __global__ __launch_bounds__(256) void k_leaf(const Bufs* __restrict__ bufs, const LeafJob* __restrict__ jobs,
                                               int j0, double* __restrict__ logdet, int* __restrict__ status) {
@@ -1838,9 +1870,11 @@ __global__ __launch_bounds__(256) void k_leaf(const Bufs* __restrict__ bufs, con
   extern __shared__ double smem[];
   double* Pn = smem;                  // LF x LPLD panel (row i at Pn[i * LPLD])
   double* dg = smem + LF * LPLD;      // diagonal of the factor
+  double* thr = dg + LF;              // zero-pivot threshold per column
   const int tid = threadIdx.x, ty = tid & 15, tx = tid >> 4;
   double* __restrict__ Dp = refp(bufs, J.D);
   const int ldd = J.D.ld, p = J.p;
+  for (int i = tid; i < p; i += 256) thr[i] = PIVOT_REL * p * fabs(Dp[i + (size_t)i * ldd]);
   double acc[8][8];
 #pragma unroll
   for (int a = 0; a < 8; ++a)
@@ -1889,7 +1923,7 @@ __global__ __launch_bounds__(256) void k_leaf(const Bufs* __restrict__ bufs, con
       for (int c = 0; c < LPW; ++c) {
         if (c < w && wbad < 0) {
           const double d = wave_bcast(x0[c], c);
-          if (!(d > 0.0) || !isfinite(d)) {
+          if (!(d > thr[jb + c]) || !isfinite(d)) {
             wbad = jb + c;
           } else {
             const double ljj = sqrt(d), inv = 1.0 / ljj;
@@ -2420,9 +2454,16 @@ __global__ __launch_bounds__(256) void k_aca(double* __restrict__ Ub, double* __
 }
 
 // ------------------------------------------------------------------ utilities
-__global__ void k_copy_rank(int* __restrict__ dyn, const int2* __restrict__ pairs, int n) {
+// After the assembly, per low-rank block (x: rank slot, y: sketch-width slot,
+// z: rank-hint slot): the sketch width of the sweep is the larger of the
+// assembled rank and the hint left by the last factorisation, plus the
+// oversampling.
+__global__ void k_copy_rank(int* __restrict__ dyn, const int4* __restrict__ slots, int n, int oversample) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dyn[pairs[i].y] = dyn[pairs[i].x];
+  if (i < n) {
+    const int4 s = slots[i];
+    dyn[s.y] = max(dyn[s.x], dyn[s.z]) + oversample;
+  }
 }
 
 // out[i] = in[perm[i]] (gather) or out[perm[i]] = in[i] (scatter)
@@ -2488,7 +2529,7 @@ __global__ void k_fill_value(double* __restrict__ out, int64_t n, double v) {
 
 constexpr size_t LDS_QR = (size_t(QR_LDS) + 8) * 8;
 constexpr size_t LDS_SMALL = (size_t(2) * SM * SM + size_t(SM) * (SM + 1) + SM + 8 + 2 * SM) * 8 + SM * 4;
-constexpr size_t LDS_LEAF = size_t(LF * LPLD + LF) * 8;
+constexpr size_t LDS_LEAF = size_t(LF * LPLD + 2 * LF) * 8;
 constexpr size_t LDS_TRSM = (size_t(LF) * (LF + 1) / 2 + size_t(LF) * 64) * 8;
 
 hipError_t setup_kernel_attributes() {
@@ -2533,7 +2574,8 @@ hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st) {
       if (n > 0) k_trmm<<<n, 256, LDS_TRSM, st>>>(L.dbufs, L.dyn, L.trsms, s.begin);
       break;
     case ST_COPY_RANK:
-      if (L.n_copy > 0) k_copy_rank<<<(L.n_copy + 255) / 256, 256, 0, st>>>(L.dyn, L.copy_pairs, L.n_copy);
+      if (L.n_copy > 0)
+        k_copy_rank<<<(L.n_copy + 255) / 256, 256, 0, st>>>(L.dyn, L.copy_pairs, L.n_copy, L.oversample);
       break;
     default:
       return hipErrorInvalidValue;

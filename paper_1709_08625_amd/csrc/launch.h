@@ -36,9 +36,10 @@ struct LaunchCtx {
   const SmallJob* smalls;
   const LeafJob* leafs;
   const TrsmJob* trsms;
-  const int2* copy_pairs;
+  const int4* copy_pairs;   // (rank, sketch width, rank hint) slots per low-rank block
   int n_copy;
   int rmax;
+  int oversample;       // sketch columns beyond the assembly rank (ST_COPY_RANK)
   double eps;
   double tau;
   double* logdet;

@@ -797,7 +797,8 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         s.p = B.r1 - B.r0;
         s.q = B.c1 - B.c0;
         int rmaxT = int(std::min<int64_t>({s.p, s.q, int64_t(P.rcap)}));
-        s.r = Dim{B.rank0_slot, P.oversample, rmaxT};
+        // after the assembly the rank0 slot holds rank + oversampling
+        s.r = Dim{B.rank0_slot, 0, rmaxT};
         s.rk = dim_dyn(dyn_alloc(), rmaxT);
         s.y = scr_alloc(s.p * rmaxT);
         s.qm = scr_alloc(s.p * rmaxT);
@@ -854,6 +855,8 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         J.C1 = Ref{B_SCR, RM, s.pm};
         J.cap = s.rk.maxv;
         J.sat = dim_static(-1);
+        J.full = 0;
+        J.hint_slot = -1;
         J.eps = -2.0;           // tau from the context at run time
         P.smalls.push_back(J);
       }
@@ -933,7 +936,9 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         J.R2 = Ref{B_SCR, RM, s.rq};
         J.C1 = Ref{B_SCR, RM, s.c2};
         J.cap = P.kcap;
-        J.sat = s.r;            // saturation if rank == r
+        J.sat = s.r;            // saturation if the kept rank nearly fills r
+        J.full = int32_t(std::min(s.p, s.q));
+        J.hint_slot = P.blocks[s.b].hint_slot;
         J.eps = -1.0;           // filled at run time from the context eps
         P.smalls.push_back(J);
       }
@@ -1049,6 +1054,8 @@ void Builder::build_recompress() {
       J.C2 = Ref{B_PERS, RM, cv[i - c0]};
       J.cap = P.kcap;
       J.sat = dim_static(-1);
+      J.full = 0;
+      J.hint_slot = -1;
       J.eps = -1.0;
       P.smalls.push_back(J);
     }
@@ -1213,15 +1220,14 @@ void Builder::build_matvec() {
 }  // namespace
 
 std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, int64_t nb,
-                       int kcap, int oversample, bool mixed) {
+                       int kcap, bool mixed) {
   P = Plan();
   P.mixed = mixed;
   P.n = n;
   P.D = D;
   P.leaf = leaf;
   P.kcap = kcap;
-  P.oversample = oversample;
-  P.rcap = kcap + oversample;
+  P.rcap = kcap + OVERSAMPLE_MAX;
   P.rmax = std::max(P.rcap, kcap);
   if (kcap > 64 || kcap < 1) return "rank capacity must be in [1, 64]";
   if (P.rmax > 80) return "rank capacity plus oversampling must not exceed 80";
@@ -1265,13 +1271,14 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
       B.off_d = -1;
       B.rank_slot = dyn++;
       B.rank0_slot = dyn++;
+      B.hint_slot = dyn++;
       P.n_lr++;
       P.lr_rows += p + q;
     } else {
       B.off_d = P.dense_elems;
       P.dense_elems += p * q;
       B.off_u = B.off_v = -1;
-      B.rank_slot = B.rank0_slot = -1;
+      B.rank_slot = B.rank0_slot = B.hint_slot = -1;
       P.n_dense++;
       if (B.level != D) return "dense block above the leaf level";
       if (B.a == B.c) P.diag_block[B.a] = int32_t(b);

@@ -104,6 +104,9 @@ struct SmallJob {
   Ref C1, C2;              // outputs (ld RMAX)
   int32_t cap;             // maximal allowed output rank
   Dim sat;                 // sketch width (saturation test); static -1 = none
+  int32_t full;            // min(p, q) of the block: a sketch this wide spans
+                           // the whole column space and cannot saturate
+  int32_t hint_slot;       // dyn slot of the block's rank hint (-1: none)
   double eps;              // < 0: taken from the launch (-1 eps, -2 tau)
 };
 
@@ -153,14 +156,16 @@ struct BlockInfo {
   int64_t off_d;               // dense offset (elements) in B_DENSE
   int64_t off_u, off_v;        // LR offsets in B_U / B_V
   int32_t rank_slot;           // dyn slot of the current rank (LR)
-  int32_t rank0_slot;          // dyn slot of the assembly rank (LR)
+  int32_t rank0_slot;          // dyn slot of the ACA rank, then of the sketch width (LR)
+  int32_t hint_slot;           // dyn slot of the rank the last factorisation kept (LR)
 };
 
 struct Plan {
   // structure
   int64_t n = 0;
   bool mixed = false;   // low-rank GEMM work in FP32 (dense leaves, potrf, solves FP64)
-  int D = 0, leaf = 0, kcap = 64, rcap = 74, oversample = 10, rmax = 80;
+  // rcap: widest randomised sketch (rank + oversampling), rmax = max(rcap, kcap)
+  int D = 0, leaf = 0, kcap = 64, rcap = 80, rmax = 80;
   std::vector<std::vector<int64_t>> lo;   // lo[l][i] node start (size 2^l + 1 incl. end)
   std::vector<BlockInfo> blocks;
   std::unordered_map<uint64_t, int32_t> status;   // (l,a,c) -> block id, or -1 = subdivided
@@ -209,8 +214,13 @@ inline uint64_t key3(int l, int64_t a, int64_t c) {
 // Build the plan from the tree structure.  blocks_lac: n_blocks x 4
 // (level, row node, col node, kind) in breadth-first order.
 // Returns an empty string on success, else an error message.
+// The sketch width of a low-rank target is the larger of its assembly rank
+// and the rank its factor block had in the last factorisation, plus an
+// oversampling chosen at run time (see ST_COPY_RANK), at most rcap =
+// kcap + OVERSAMPLE_MAX.
+constexpr int OVERSAMPLE_MAX = 16;
 std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blocks_lac,
-                       int64_t n_blocks, int kcap, int oversample, bool mixed);
+                       int64_t n_blocks, int kcap, bool mixed);
 
 int64_t node_lo(const Plan& P, int l, int64_t i);
 int64_t node_hi(const Plan& P, int l, int64_t i);

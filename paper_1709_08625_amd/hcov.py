@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libhcov.so")
 OK, EINVAL, ENOTSPD, ENOMEM, ESTATE, EDEVICE, ERANK = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
 FP64, MIXED = 0, 1
+SAT_RETRY, SAT_ERROR = 0, 1
 
 
 class Theta(C.Structure):
@@ -39,7 +40,8 @@ class Result(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("max_rank", C.c_int), ("aca_eps_factor", C.c_double),
                 ("fuse_solve", C.c_int), ("mem_cap_bytes", C.c_size_t), ("alloc", ALLOC_FN),
-                ("free", FREE_FN), ("alloc_user", C.c_void_p), ("use_graphs", C.c_int)]
+                ("free", FREE_FN), ("alloc_user", C.c_void_p), ("use_graphs", C.c_int),
+                ("oversample", C.c_int), ("on_saturation", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -48,7 +50,8 @@ class Stats(C.Structure):
                 ("max_rank_seen", C.c_int), ("mean_rank", C.c_double), ("bytes_device", C.c_int64),
                 ("bytes_factor", C.c_int64), ("ms_tree", C.c_double), ("ms_assemble", C.c_double),
                 ("ms_factor", C.c_double), ("ms_solve", C.c_double), ("n_steps", C.c_int64),
-                ("n_launches_factor", C.c_int64), ("n_graph_replays", C.c_int64)]
+                ("n_launches_factor", C.c_int64), ("n_graph_replays", C.c_int64),
+                ("n_sketch_retries", C.c_int64), ("sketch_saturated", C.c_int), ("mean_sketch_width", C.c_double)]
 
 
 _lib = None

@@ -45,7 +45,10 @@ def test_graph_replays_match_stage_launches(hcov, n, leaf, eps):
     G.cholesky()
     E.cholesky()
     assert G.logdet() == E.logdet()
-    assert G.stats()["n_graph_replays"] == 5
+    # every factorisation of G (the retries of saturated sketches included) replays
+    st = G.stats()
+    assert st["n_graph_replays"] == 5 + st["n_sketch_retries"]
+    assert st["n_sketch_retries"] == E.stats()["n_sketch_retries"]
     assert E.stats()["n_graph_replays"] == 0
     G.close()
     E.close()

@@ -30,3 +30,15 @@ def test_library_nm_matches_oracle_history(fname):
 def test_library_nm_rejects_bad_arguments():
     with pytest.raises(hcov.HcovError):
         hcov.nm_minimize(lambda x: 0.0, np.zeros(3), [0.1, 0.1, 0.1], max_evals=0)
+
+
+@pytest.mark.parametrize("move", ["reflection", "expansion", "outside", "inside", "shrink"])
+def test_library_nm_single_moves_by_hand(move):
+    # the hand-worked single moves of the method (tests/test_oracle_nm.py),
+    # checked on the library directly so that a mistake shared with the
+    # oracle's implementation cannot hide
+    from tests.test_oracle_nm import MOVES
+
+    f, cap, want = MOVES[move]
+    _, _, n, hist = hcov.nm_minimize(f, np.zeros(2), [1.0, 1.0], max_evals=cap, size_tol=0.0)
+    assert [tuple(float(c) for c in x) for x, _ in hist] == want

@@ -197,3 +197,46 @@ def test_config1_anchor():
     assert abs(q - float(xi @ xi)) < 1e-8 * q
     n = 2000
     assert abs(ll - (-0.5 * n * math.log(2 * math.pi) - 0.5 * ld - 0.5 * q)) < 1e-9
+
+
+# ---------------------------------------------------------------- dense.solve
+def test_dense_solve_two_points_closed_form():
+    # n = 2: C = [[a, b], [b, a]] with a = sigma^2 + tau^2, b = C(h); its
+    # inverse is [[a, -b], [-b, a]] / (a^2 - b^2)
+    locs = np.array([[0.1, 0.2], [0.4, 0.6]])
+    s2, ell, nu, tau2 = 1.3, 0.2, 0.5, 0.05
+    b = s2 * math.exp(-0.5 / ell)            # h = 0.5, exponential kernel (nu = 1/2)
+    a = s2 + tau2
+    z = np.array([0.7, -1.1])
+    want = np.array([a * z[0] - b * z[1], -b * z[0] + a * z[1]]) / (a * a - b * b)
+    np.testing.assert_allclose(dense.solve(locs, z, s2, ell, nu, tau2), want, rtol=1e-14)
+
+
+def test_dense_solve_residual_and_quadratic_form():
+    # x = C^{-1} z solves C x = z (residual at rounding level for a well
+    # conditioned C) and z^T x is the quadratic form of Eq. (1)
+    locs, xi = workloads.uniform(400, seed=4)
+    th = (1.1, 0.07, 1.3, 1e-2)
+    x = dense.solve(locs, xi, *th)
+    C = dense.cov_matrix(locs, *th)
+    assert np.linalg.norm(C @ x - xi) <= 1e-12 * np.linalg.norm(C, 2) * np.linalg.norm(x)
+    _, _, q = dense.loglik_parts(locs, xi, *th)
+    assert abs(float(xi @ x) - q) <= 1e-10 * q
+
+
+# ---------------------------------------------------------------- config-1 anchor
+def test_config1_anchor_values():
+    # n = 2000 locations U([0,1]^2) and xi from default_rng(0) (locations first),
+    # Z = L xi with the exact factor; theta = (1, 0.1, 0.5), nugget 1e-4.  The
+    # values were computed independently (dense FP64 with LAPACK, outside this
+    # oracle) when the workloads were specified: logdet -3388.72409326966,
+    # q 1968.12766144384, L -1127.57885049644.
+    locs, xi = workloads.uniform(2000, seed=0)
+    th = (1.0, 0.1, 0.5, 1e-4)
+    z = dense.sample_field(locs, xi, *th)
+    ll, ld, q = dense.loglik_parts(locs, z, *th)
+    assert abs(ld - (-3388.72409326966)) < 2e-9 * 3388.7
+    assert abs(q - 1968.12766144384) < 2e-9 * 1968.1
+    assert abs(ll - (-1127.57885049644)) < 2e-9 * 1127.6
+    # and q = ||xi||^2 exactly up to rounding when Z = L xi
+    assert abs(q - float(xi @ xi)) < 1e-9 * q
