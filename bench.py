@@ -271,7 +271,8 @@ def main():
                       "mean_rank": st["mean_rank"], "max_rank": st["max_rank_seen"],
                       "factor_GB": st["bytes_factor"] / 1e9, "device_GB": st["bytes_device"] / 1e9,
                       "launches_per_factorisation": st["n_launches_factor"],
-                      "sketch_retries": st["n_sketch_retries"]},
+                      "sketch_retries": st["n_sketch_retries"],
+                      "mean_sketch_width": st["mean_sketch_width"]},
         # FP64 tiles of k_gemm run on the matrix cores (dense FP64 MFMA peak);
         # in mixed precision part of the work is FP32 but the FP64 peak is kept
         "roofline": {"bound": "mfma" if args.profile_kind == "gemm" else "alu", "kernel": f"k_{args.profile_kind}",

@@ -53,7 +53,8 @@ extern "C" {
 #define HCOV_DEVICE 1
 
 #define HCOV_FP64 0         /* every step in FP64 */
-#define HCOV_MIXED 1        /* low-rank factors/updates FP32; diagonal, logdet, quad FP64 */
+#define HCOV_MIXED 1        /* low-rank factors/updates FP32; diagonal, logdet, quad FP64;
+                               low-rank truncations at max(eps, 1e-6) */
 
 /* Matérn parameters, Eq. (3) [HLIBCov Sec. 2.1], with named fields:
  * sigma2 = sigma^2 > 0 (variance), ell > 0 (range; the kernel argument is
@@ -89,10 +90,9 @@ typedef struct {
   int oversample;         /* columns of a low-rank target's randomised sketch
                              in the factorisation's recompression beyond its
                              rank estimate (the larger of the block's assembled
-                             rank and the rank its factor block kept in the
-                             context's last factorisation); default 10, range
-                             [2, 64]; the width is capped at max_rank + 16 and
-                             at min(rows, cols) of the block */
+                             rank and its rank hint, see hcov_cholesky);
+                             default 10, range [2, 64]; the width is capped at
+                             max_rank + 16 and at min(rows, cols) of the block */
   int on_saturation;      /* HCOV_SAT_RETRY (default) or HCOV_SAT_ERROR: what a
                              saturated sketch does, see hcov_cholesky */
 } hcov_opts;
@@ -173,13 +173,16 @@ int hcov_set_theta(hcov_ctx* ctx, hcov_theta theta);
  * randomised sketch (width: see opts.oversample).  When a block keeps a rank
  * of at least the width minus one while the sketch is narrower than the
  * block, the sketch is saturated and eps is no longer guaranteed for that
- * block; its rank hint is then doubled.  With HCOV_SAT_RETRY the matrix is
- * re-assembled and the factorisation redone with the wider sketches, up to 4
- * times; a sketch saturated at the widest width (max_rank + 16), saturation
- * after the last retry, or any saturation with HCOV_SAT_ERROR returns
- * HCOV_ERANK.  The factorisation is never reported as done (HCOV_OK) with a
- * saturated sketch.  Rank hints persist in the context, so later
- * factorisations (new theta) start from the ranks the last one needed. */
+ * block.  After such a factorisation every block's rank hint becomes the
+ * rank it kept, 1.5 times its sketch width plus 2 where the sketch
+ * saturated.  With
+ * HCOV_SAT_RETRY the matrix is re-assembled and the factorisation redone
+ * with the new widths, up to 4 times; a sketch saturated at the widest width
+ * (max_rank + 16), saturation after the last retry, or any saturation with
+ * HCOV_SAT_ERROR returns HCOV_ERANK.  The factorisation is never reported as
+ * done (HCOV_OK) with a saturated sketch.  The hints persist in the context
+ * and change only after a saturated factorisation: later factorisations (new
+ * theta) start from them, and repeating an evaluation gives the same bits. */
 int hcov_cholesky(hcov_ctx* ctx);
 
 /* log|C~| = 2 sum_i log L~_ii [HLIBCov Eq. (2)], FP64 reduction in a fixed

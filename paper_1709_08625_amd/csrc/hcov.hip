@@ -256,6 +256,7 @@ double stage_flops(const Plan& P, const std::vector<int>& dyn, const Stage& s) {
 // below the widest width: the saturated blocks' rank hints were doubled, and
 // the caller re-assembles and factorises again with the wider sketches.
 constexpr int SAT_RETRY = 1;
+constexpr double MIXED_EPS_FLOOR = 1e-6;
 constexpr int MAX_SKETCH_RETRIES = 4;
 
 int check_status(hcov_ctx* c, bool spd_matters) {
@@ -269,6 +270,9 @@ int check_status(hcov_ctx* c, bool spd_matters) {
     c->factored = false;
     if (st[0] & STAT_SAT_CAP)
       return fail(c, HCOV_ERANK, "a low-rank block's randomised sketch saturated at the widest width (max_rank + 16)");
+    // the saturated blocks' doubled widths (and every other block's kept rank)
+    // become the hints of the next factorisation, retried here or later
+    HIPCHK(c, launch_adopt_hints(c->L, c->stream));
     if (c->opts.on_saturation == HCOV_SAT_RETRY) return SAT_RETRY;
     return fail(c, HCOV_ERANK, "a low-rank block's randomised sketch saturated (on_saturation = HCOV_SAT_ERROR)");
   }
@@ -635,7 +639,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
       fj.push_back(FillJob{B.off_d, B.r0, B.c0, int32_t(B.r1 - B.r0), int32_t(B.c1 - B.c0), B.a == B.c ? 1 : 0, 0});
     } else {
       aj.push_back(AcaJob{B.off_u, B.off_v, B.r0, B.c0, int32_t(B.r1 - B.r0), int32_t(B.c1 - B.c0), B.rank0_slot, 0});
-      cp.push_back(make_int4(B.rank_slot, B.rank0_slot, B.hint_slot, 0));
+      cp.push_back(make_int4(B.rank_slot, B.rank0_slot, B.hint_slot, B.cand_slot));
     }
   }
   // blocks with more than ACA_BIG_SPLIT rows + columns: multi-work-group ACA
@@ -698,7 +702,10 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   L.n_copy = int(cp.size());
   L.rmax = P.rmax;
   L.oversample = o.oversample;
-  L.eps = eps;
+  // FP32 accumulation leaves noise of order 1e-7 relative in the low-rank
+  // products: in mixed precision the truncations keep singular values above
+  // max(eps, 1e-6) of the largest, so that noise is not kept as rank
+  L.eps = o.precision == HCOV_MIXED ? std::max(eps, MIXED_EPS_FLOOR) : eps;
   L.tau = std::min(1e-10, 1e-2 * eps);
   L.logdet = c->d_logdet;
   L.status = c->d_status;

@@ -1453,8 +1453,8 @@ __device__ __forceinline__ bool sketch_saturated(int kept, int r, int full) {
 }
 
 // Truncation result of a sketched low-rank target (one thread): the kept rank
-// becomes the block's rank hint for the sketch width of the next
-// factorisation; a saturated sketch doubles the hint and raises
+// is the block's candidate rank hint for the next factorisation's sketch
+// width; a saturated sketch proposes 1.5 times its width plus 2 and raises
 // STAT_SKETCH_SAT (and STAT_SAT_CAP when the sketch was already as wide as
 // the plan allows).
 __device__ __forceinline__ void sketch_report(const SmallJob& J, int* __restrict__ dyn, int kept,
@@ -1462,7 +1462,7 @@ __device__ __forceinline__ void sketch_report(const SmallJob& J, int* __restrict
   if (J.sat.maxv < 0) return;
   const int r = dimv(dyn, J.sat);
   const bool sat = sketch_saturated(kept, r, J.full);
-  if (J.hint_slot >= 0) dyn[J.hint_slot] = sat ? 2 * r : kept;
+  if (J.cand_slot >= 0) dyn[J.cand_slot] = sat ? r + r / 2 + 2 : kept;
   if (sat) {
     atomicOr(status, r >= J.sat.maxv ? (STAT_SKETCH_SAT | STAT_SAT_CAP) : STAT_SKETCH_SAT);
     atomicAdd(status + 2, 1);   // saturated blocks of this factorisation
@@ -2455,15 +2455,21 @@ __global__ __launch_bounds__(256) void k_aca(double* __restrict__ Ub, double* __
 
 // ------------------------------------------------------------------ utilities
 // After the assembly, per low-rank block (x: rank slot, y: sketch-width slot,
-// z: rank-hint slot): the sketch width of the sweep is the larger of the
-// assembled rank and the hint left by the last factorisation, plus the
-// oversampling.
+// z: rank-hint slot, w: candidate-hint slot): the sketch width of the sweep
+// is the larger of the assembled rank and the hint, plus the oversampling.
 __global__ void k_copy_rank(int* __restrict__ dyn, const int4* __restrict__ slots, int n, int oversample) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const int4 s = slots[i];
     dyn[s.y] = max(dyn[s.x], dyn[s.z]) + oversample;
   }
+}
+
+// After a factorisation whose sketches saturated: the candidate hints it
+// wrote become the rank hints.
+__global__ void k_adopt_hints(int* __restrict__ dyn, const int4* __restrict__ slots, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dyn[slots[i].z] = dyn[slots[i].w];
 }
 
 // out[i] = in[perm[i]] (gather) or out[perm[i]] = in[i] (scatter)
@@ -2580,6 +2586,11 @@ hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st) {
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_adopt_hints(const LaunchCtx& L, hipStream_t st) {
+  if (L.n_copy > 0) k_adopt_hints<<<(L.n_copy + 255) / 256, 256, 0, st>>>(L.dyn, L.copy_pairs, L.n_copy);
   return hipGetLastError();
 }
 

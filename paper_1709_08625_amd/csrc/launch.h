@@ -36,7 +36,7 @@ struct LaunchCtx {
   const SmallJob* smalls;
   const LeafJob* leafs;
   const TrsmJob* trsms;
-  const int4* copy_pairs;   // (rank, sketch width, rank hint) slots per low-rank block
+  const int4* copy_pairs;   // (rank, sketch width, rank hint, candidate hint) slots per low-rank block
   int n_copy;
   int rmax;
   int oversample;       // sketch columns beyond the assembly rank (ST_COPY_RANK)
@@ -64,6 +64,7 @@ hipError_t run_aca_big(double* U, double* V, int* dyn, const double* loc, const 
 
 hipError_t setup_kernel_attributes();
 hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st);
+hipError_t launch_adopt_hints(const LaunchCtx& L, hipStream_t st);
 hipError_t launch_fill(double* D, const double* loc, const FillJob* jobs, int njobs,
                        const MaternParams& P, hipStream_t st);
 hipError_t launch_aca(double* U, double* V, int* dyn, const double* loc, const AcaJob* jobs, int njobs,

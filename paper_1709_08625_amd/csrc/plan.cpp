@@ -856,7 +856,7 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         J.cap = s.rk.maxv;
         J.sat = dim_static(-1);
         J.full = 0;
-        J.hint_slot = -1;
+        J.cand_slot = -1;
         J.eps = -2.0;           // tau from the context at run time
         P.smalls.push_back(J);
       }
@@ -938,7 +938,7 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         J.cap = P.kcap;
         J.sat = s.r;            // saturation if the kept rank nearly fills r
         J.full = int32_t(std::min(s.p, s.q));
-        J.hint_slot = P.blocks[s.b].hint_slot;
+        J.cand_slot = P.blocks[s.b].cand_slot;
         J.eps = -1.0;           // filled at run time from the context eps
         P.smalls.push_back(J);
       }
@@ -1055,7 +1055,7 @@ void Builder::build_recompress() {
       J.cap = P.kcap;
       J.sat = dim_static(-1);
       J.full = 0;
-      J.hint_slot = -1;
+      J.cand_slot = -1;
       J.eps = -1.0;
       P.smalls.push_back(J);
     }
@@ -1272,13 +1272,14 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
       B.rank_slot = dyn++;
       B.rank0_slot = dyn++;
       B.hint_slot = dyn++;
+      B.cand_slot = dyn++;
       P.n_lr++;
       P.lr_rows += p + q;
     } else {
       B.off_d = P.dense_elems;
       P.dense_elems += p * q;
       B.off_u = B.off_v = -1;
-      B.rank_slot = B.rank0_slot = B.hint_slot = -1;
+      B.rank_slot = B.rank0_slot = B.hint_slot = B.cand_slot = -1;
       P.n_dense++;
       if (B.level != D) return "dense block above the leaf level";
       if (B.a == B.c) P.diag_block[B.a] = int32_t(b);

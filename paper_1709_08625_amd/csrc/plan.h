@@ -106,7 +106,7 @@ struct SmallJob {
   Dim sat;                 // sketch width (saturation test); static -1 = none
   int32_t full;            // min(p, q) of the block: a sketch this wide spans
                            // the whole column space and cannot saturate
-  int32_t hint_slot;       // dyn slot of the block's rank hint (-1: none)
+  int32_t cand_slot;       // dyn slot of the block's candidate rank hint (-1: none)
   double eps;              // < 0: taken from the launch (-1 eps, -2 tau)
 };
 
@@ -157,7 +157,8 @@ struct BlockInfo {
   int64_t off_u, off_v;        // LR offsets in B_U / B_V
   int32_t rank_slot;           // dyn slot of the current rank (LR)
   int32_t rank0_slot;          // dyn slot of the ACA rank, then of the sketch width (LR)
-  int32_t hint_slot;           // dyn slot of the rank the last factorisation kept (LR)
+  int32_t hint_slot;           // dyn slot of the rank hint of the sweep's sketch width (LR)
+  int32_t cand_slot;           // dyn slot of the rank the last factorisation kept (LR)
 };
 
 struct Plan {
@@ -215,9 +216,12 @@ inline uint64_t key3(int l, int64_t a, int64_t c) {
 // (level, row node, col node, kind) in breadth-first order.
 // Returns an empty string on success, else an error message.
 // The sketch width of a low-rank target is the larger of its assembly rank
-// and the rank its factor block had in the last factorisation, plus an
-// oversampling chosen at run time (see ST_COPY_RANK), at most rcap =
-// kcap + OVERSAMPLE_MAX.
+// and its rank hint, plus an oversampling chosen at run time (see
+// ST_COPY_RANK), at most rcap = kcap + OVERSAMPLE_MAX.  A factorisation
+// writes every target's kept rank (doubled sketch width where the sketch
+// saturated) as its candidate hint; the candidates become the hints only
+// after a factorisation that saturated, so that the widths, and with them
+// the results, change only when a sketch was too narrow.
 constexpr int OVERSAMPLE_MAX = 16;
 std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blocks_lac,
                        int64_t n_blocks, int kcap, bool mixed);

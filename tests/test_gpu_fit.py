@@ -21,20 +21,25 @@ def test_fit_matches_python_driven_search_and_dense_optimum():
     theta0 = np.array([1.2, 0.08, 1.32])          # truth x (1.2, 0.8, 1.1)
     steps = [0.01, 0.04, 0.02]
     evals = 40
+    # two contexts built the same way: a context keeps the rank hints of its
+    # last factorisation (they set the sketch widths of the next one), so two
+    # searches agree bit for bit when each starts from a fresh context
     H = hcov.HCov(locs, (*theta0, nug), eps=eps, leaf=leaf, eta=2.0)
+    H2 = hcov.HCov(locs, (*theta0, nug), eps=eps, leaf=leaf, eta=2.0)
     try:
         th, ll, ne, hist = H.fit(z, theta0, nug, max_evals=evals, steps=steps)
 
         def f(x):
             try:
-                H.set_theta((x[0], x[1], x[2], nug))
-                return -H.loglik(z)[0]
+                H2.set_theta((x[0], x[1], x[2], nug))
+                return -H2.loglik(z)[0]
             except hcov.HcovError:
                 return float("inf")
 
         th2, f2, ne2, hist2 = hcov.nm_minimize(f, theta0, steps, max_evals=evals)
     finally:
         H.close()
+        H2.close()
     assert ne == ne2 == evals
     for (a, fa), (b, fb) in zip(hist, hist2):
         assert np.array_equal(a, b) and fa == fb
