@@ -274,6 +274,19 @@ int hcov_profile_end(hcov_ctx* ctx, int64_t* launches, double* total_ms, double*
  * the device Matérn / K_nu evaluation used by the assembly. */
 int hcov_matern_eval(hcov_theta theta, const double* h, double* out, int64_t n);
 
+/* hcov_matern_eval without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture elsewhere in the process, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments and result
+ * as hcov_matern_eval (host arrays h, out of n doubles), on the current
+ * device and its null stream.  The device staging of h and out lives in a
+ * fixed array of HCOV_NOALLOC_MAX_N x 2 doubles (4 MiB) that each GPU holds
+ * for the life of the process; n > HCOV_NOALLOC_MAX_N returns HCOV_EINVAL
+ * before any device work.  Calls on one GPU share that array: calls from
+ * threads of this process are serialised by a per-device lock, calls that
+ * overlap from other code paths on the same array race. */
+#define HCOV_NOALLOC_MAX_N 262144
+int hcov_matern_eval_noalloc(hcov_theta theta, const double* h, double* out, int64_t n);
+
 const char* hcov_strerror(int code);
 const char* hcov_last_error(const hcov_ctx* ctx);
 

@@ -1012,3 +1012,38 @@ int hcov_matern_eval(hcov_theta theta, const double* h, double* out, int64_t n) 
 }
 
 }  // extern "C"
+// ------------------------------------------------------------ no-allocation variant
+// hcov_matern_eval without any allocation: the device staging of distances
+// and results lives in a fixed array of this library (each GPU holds its own
+// copy), whose device address is looked up once per device.
+namespace {
+constexpr int64_t NOALLOC_MAX = HCOV_NOALLOC_MAX_N;
+__device__ __align__(256) double scratch[2 * NOALLOC_MAX];   // [0, MAX): h, [MAX, 2 MAX): out
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu[MAX_DEVICES];
+double* scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+extern "C" int hcov_matern_eval_noalloc(hcov_theta theta, const double* h, double* out, int64_t n) {
+  if (!h || !out || n < 0 || !theta_ok(theta) || n > NOALLOC_MAX) return HCOV_EINVAL;
+  if (n == 0) return HCOV_OK;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return HCOV_EDEVICE;
+  std::lock_guard<std::mutex> lock(scratch_mu[dev]);
+  if (!scratch_ptr[dev]) {
+    // the host-side name `scratch` is not a device address: resolve it once
+    // per device, with that device current
+    double* p = nullptr;
+    if (hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HCOV_EDEVICE;
+    scratch_ptr[dev] = p;
+  }
+  double* dh = scratch_ptr[dev];
+  double* dout = dh + NOALLOC_MAX;
+  const MaternParams P = make_params(theta);
+  if (hipMemcpyAsync(dh, h, size_t(n) * 8, hipMemcpyHostToDevice, nullptr) != hipSuccess ||
+      launch_probe(dh, dout, n, P, nullptr) != hipSuccess ||
+      hipMemcpyAsync(out, dout, size_t(n) * 8, hipMemcpyDeviceToHost, nullptr) != hipSuccess ||
+      hipStreamSynchronize(nullptr) != hipSuccess)
+    return HCOV_EDEVICE;
+  return HCOV_OK;
+}
