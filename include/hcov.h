@@ -95,7 +95,28 @@ typedef struct {
                              max_rank + 16 and at min(rows, cols) of the block */
   int on_saturation;      /* HCOV_SAT_RETRY (default) or HCOV_SAT_ERROR: what a
                              saturated sketch does, see hcov_cholesky */
+  int keep_matrix;        /* 1: keep a copy of the assembled C~ (dense and
+                             low-rank arenas, about the size of the factor)
+                             so that hcov_matvec, hcov_error_norms and the PCG
+                             quadratic form work after the factorisation
+                             (default 0; implied by HCOV_QUAD_PCG) */
+  int quad_mode;          /* HCOV_QUAD_DIRECT (default): z^T C~^{-1} z as
+                             v^T v with L~ v = z [Eq. (2)]; HCOV_QUAD_PCG:
+                             z^T x with C~ x = z solved by conjugate
+                             gradients on C~ preconditioned by L~ L~^T (the
+                             listing of Appendix B) */
+  double pcg_tol;         /* PCG stop: ||z - C~ x|| <= pcg_tol ||z|| (default
+                             1e-6, the listing's tolerance) */
+  int pcg_max_iter;       /* PCG iteration cap (default 150, the listing's) */
+  int fixed_rank;         /* 0 (default): fixed accuracy eps; k > 0: every
+                             low-rank block of C~ and of the factor keeps at
+                             most k singular values above eps sigma_1 (the
+                             fixed-rank H-matrices of Sec. 3, Tables 2 and 3);
+                             k <= max_rank, and reaching it is no error */
 } hcov_opts;
+
+#define HCOV_QUAD_DIRECT 0
+#define HCOV_QUAD_PCG 1
 
 #define HCOV_SAT_RETRY 0
 #define HCOV_SAT_ERROR 1
@@ -120,6 +141,8 @@ typedef struct {
   int64_t n_sketch_retries;   /* factorisations redone with wider sketches */
   int sketch_saturated;       /* saturated sketches in the last factorisation */
   double mean_sketch_width;   /* mean sketch width of the low-rank blocks */
+  int pcg_iters;              /* PCG iterations of the last quadratic form */
+  double pcg_relres;          /* its final ||z - C~ x|| / ||z|| */
 } hcov_stats_t;
 
 typedef struct hcov_ctx hcov_ctx;
@@ -204,8 +227,40 @@ int hcov_forward(hcov_ctx* ctx, const double* z, double* v, double* quad, int wh
 int hcov_sample(hcov_ctx* ctx, const double* xi, double* y, int where);
 
 /* y = C~ x (H-matrix times vector, [HLIBCov Table 1 "C~ z"]), external order.
- * Requires an assembled, not yet factorised context (else HCOV_ESTATE). */
+ * Requires an assembled, not yet factorised context, or opts.keep_matrix
+ * (else HCOV_ESTATE). */
 int hcov_matvec(hcov_ctx* ctx, const double* x, double* y, int where);
+
+/* y = L~ L~^T x (the factorised matrix times a vector, external order;
+ * the factor's product with a vector of [HLIBCov Table 1]).  Requires
+ * hcov_cholesky and opts.keep_matrix (for the vector workspace). */
+int hcov_factor_matvec(hcov_ctx* ctx, const double* x, double* y, int where);
+
+/* Accuracy of the factorisation by power iteration [HLIBCov Sec. 3, the error
+ * columns of Tables 2, 3 and 5], each from its own seeded Gaussian start
+ * vector and `iters` iterations (each estimate is a lower bound that
+ * increases towards the norm):
+ *   norm_c   = ||C~||_2,
+ *   err_fact = ||C~ - L~ L~^T||_2,
+ *   err_inv  = ||I - (L~ L~^T)^{-1} C~||_2 (power iteration on A^T A).
+ * Requires a factorised context built with opts.keep_matrix.  Any output
+ * pointer may be NULL. */
+int hcov_error_norms(hcov_ctx* ctx, int iters, uint64_t seed, double* norm_c, double* err_fact,
+                     double* err_inv);
+
+/* y = C x with the exact entries of Eq. (3) evaluated on the fly on the
+ * device (O(n^2) Matérn evaluations, no storage), external order: the
+ * reference the H-matrix approximates. */
+int hcov_exact_matvec(hcov_ctx* ctx, const double* x, double* y, int where);
+
+/* Approximation errors against the exact C of Eq. (3) by power iteration
+ * with exact products (hcov_exact_matvec), as the error columns of
+ * [HLIBCov Tables 2 and 3]:
+ *   err_c    = ||C - C~||_2,
+ *   err_cinv = ||C (L~ L~^T)^{-1} - I||_2 (the factor's inverse standing for
+ *              C~^{-1}; power iteration on B^T B).
+ * Requires a factorised context built with opts.keep_matrix. */
+int hcov_exact_norms(hcov_ctx* ctx, int iters, uint64_t seed, double* err_c, double* err_cinv);
 
 /* H-log-likelihood of Eq. (2) [HLIBCov Sec. 1]:
  *   L~ = -n/2 log(2 pi) - sum_i log L~_ii - 1/2 v^T v,  L~ v = z,

@@ -29,6 +29,17 @@ def distances(locs):
     return np.sqrt(dx * dx + dy * dy)
 
 
+def cov_block(locs_a, locs_b, sigma2, ell, nu):
+    """Block C(||a_i - b_j||) of Eq. (3) between two location sets (no
+    nugget): the entries of cov_matrix for rows a and columns b, for
+    assembling large dense matrices a block of rows at a time."""
+    a = np.asarray(locs_a, dtype=np.float64)
+    b = np.asarray(locs_b, dtype=np.float64)
+    dx = a[:, 0][:, None] - b[:, 0][None, :]
+    dy = a[:, 1][:, None] - b[:, 1][None, :]
+    return matern(np.sqrt(dx * dx + dy * dy), sigma2, ell, nu)
+
+
 def cov_matrix(locs, sigma2, ell, nu, nugget):
     """Dense C(theta) + tau^2 I (Eq. (3) entries; nugget on the diagonal)."""
     C = matern(distances(locs), sigma2, ell, nu)
@@ -59,6 +70,22 @@ def cholesky_unblocked(C):
 def cholesky_lapack(C):
     """Lower Cholesky by LAPACK dpotrf (scipy)."""
     return linalg.cholesky(np.asarray(C, dtype=np.float64), lower=True)
+
+
+def cholesky_torch(C):
+    """Lower Cholesky by LAPACK dpotrf through PyTorch's CPU backend (MKL).
+    The same factorisation as cholesky_lapack; used for n >= 32768, where the
+    OpenBLAS build behind NumPy/SciPy in this environment fails."""
+    import torch
+    return torch.linalg.cholesky(torch.from_numpy(np.ascontiguousarray(C, dtype=np.float64))).numpy()
+
+
+def forward_solve_torch(L, z):
+    """Solve L v = z by LAPACK triangular solve through PyTorch (MKL)."""
+    import torch
+    Lt = torch.from_numpy(np.ascontiguousarray(L, dtype=np.float64))
+    zt = torch.from_numpy(np.ascontiguousarray(z, dtype=np.float64)).reshape(-1, 1)
+    return torch.linalg.solve_triangular(Lt, zt, upper=False).reshape(-1).numpy()
 
 
 def forward_solve_unblocked(L, z):

@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_acab_col(double* __restrict__ Ub, doubl
 __global__ void k_acab_update(double* __restrict__ Vb, const AcaJob* __restrict__ jobs,
                               AcaBigState* __restrict__ st, const int* __restrict__ col_first,
                               const int* __restrict__ col_count, const double* __restrict__ part,
-                              const double* __restrict__ acc, int nj, double eps_aca, int kcap,
+                              const double* __restrict__ acc, int nj, double eps_aca, int kcap, int cap_ok,
                               int* __restrict__ dyn, int* __restrict__ status, int* __restrict__ active) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nj) return;
@@ -290,7 +290,7 @@ __global__ void k_acab_update(double* __restrict__ Vb, const AcaJob* __restrict_
     bool stop = sqrt(nuv) <= eps_aca * sqrt(fmax(S.nrm2, 0.0));
     const int kmax = min(min(J.p, J.q), kcap);
     if (S.k >= kmax) {
-      if (!stop && kmax < min(J.p, J.q)) atomicOr(status, STAT_RANK_OVERFLOW);
+      if (!stop && kmax < min(J.p, J.q) && !cap_ok) atomicOr(status, STAT_RANK_OVERFLOW);
       stop = true;
     }
     if (!stop) {
@@ -336,7 +336,7 @@ hipError_t run_aca_big(double* U, double* V, int* dyn, const double* loc, const 
                        const AcaBigChunk* d_rows, int nrow, const AcaBigChunk* d_cols, int ncol,
                        const int* d_row_first, const int* d_row_count, const int* d_col_first,
                        const int* d_col_count, AcaBigState* d_state, double* d_part, double* d_acc,
-                       int* d_active, const MaternParams& P, double eps_aca, int kcap, int* status,
+                       int* d_active, const MaternParams& P, double eps_aca, int kcap, int cap_ok, int* status,
                        hipStream_t st) {
   if (nj <= 0) return hipSuccess;
   k_acab_init<<<(nj + 255) / 256, 256, 0, st>>>(d_state, nj);
@@ -349,7 +349,7 @@ hipError_t run_aca_big(double* U, double* V, int* dyn, const double* loc, const 
     hipError_t e = hipMemsetAsync(d_active, 0, 4, st);
     if (e != hipSuccess) return e;
     k_acab_update<<<(nj + 127) / 128, 128, 0, st>>>(V, d_jobs, d_state, d_col_first, d_col_count, d_part, d_acc,
-                                                      nj, eps_aca, kcap, dyn, status, d_active);
+                                                      nj, eps_aca, kcap, cap_ok, dyn, status, d_active);
     k_acab_scale<<<nrow, 256, 0, st>>>(V, d_jobs, d_state, d_rows, s);
     e = hipGetLastError();
     if (e != hipSuccess) return e;

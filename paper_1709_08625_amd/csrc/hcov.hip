@@ -55,6 +55,15 @@ struct hcov_ctx {
   double *d_bpart = nullptr, *d_bacc = nullptr;
   int* d_bactive = nullptr;
   LaunchCtx L{};
+  // a copy of the assembled C~ (opts.keep_matrix): its dense and low-rank
+  // arenas and dynamic dimensions, and the launch context that addresses them
+  bool keep = false, kept_valid = false;
+  double* d_keep[3] = {};      // dense, U, V
+  int* d_dyn_keep = nullptr;
+  LaunchCtx Lc{};
+  double* d_vec = nullptr;     // 6 n doubles: vectors of the iterations (PCG, power method)
+  int pcg_iters = 0;
+  double pcg_relres = 0.0;
   // kernel profiling (HIP events around every launch of one stage kind)
   int prof_kind = -1;
   // second lane of the factorisation sweep (see ST_FORK / ST_JOIN)
@@ -183,7 +192,8 @@ int tree_depth(int64_t n, int leaf) {
   return D;
 }
 
-int run_stages(hcov_ctx* c, const std::vector<Stage>& st) {
+int run_stages(hcov_ctx* c, const std::vector<Stage>& st, const LaunchCtx* Lx = nullptr) {
+  const LaunchCtx& LC = Lx ? *Lx : c->L;
   for (const Stage& s : st) {
     if (s.kind == ST_FORK) {
       HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
@@ -201,12 +211,12 @@ int run_stages(hcov_ctx* c, const std::vector<Stage>& st) {
       HIPCHK(c, hipEventCreate(&a));
       HIPCHK(c, hipEventCreate(&b));
       HIPCHK(c, hipEventRecord(a, sm));
-      HIPCHK(c, launch_stage(s, c->L, sm));
+      HIPCHK(c, launch_stage(s, LC, sm));
       HIPCHK(c, hipEventRecord(b, sm));
       c->prof_ev.emplace_back(a, b);
       c->prof_stages.push_back(s);
     } else {
-      HIPCHK(c, launch_stage(s, c->L, sm));
+      HIPCHK(c, launch_stage(s, LC, sm));
     }
   }
   return HCOV_OK;
@@ -301,26 +311,40 @@ int assemble(hcov_ctx* c) {
   int r = reset_status(c);
   if (r) return r;
   HIPCHK(c, launch_fill(c->d_buf[B_DENSE], c->d_loc, c->d_fill, c->n_fill, c->mp, c->stream));
+  const int cap_ok = c->opts.fixed_rank > 0 ? 1 : 0;
   HIPCHK(c, launch_aca(c->d_buf[B_U], c->d_buf[B_V], c->d_dyn, c->d_loc, c->d_aca, c->n_aca, c->mp,
-                       c->eps * c->opts.aca_eps_factor, c->plan.kcap, c->d_status, c->stream));
+                       c->eps * c->opts.aca_eps_factor, c->plan.kcap, cap_ok, c->d_status, c->stream));
   HIPCHK(c, run_aca_big(c->d_buf[B_U], c->d_buf[B_V], c->d_dyn, c->d_loc, c->d_acab, c->n_acab, c->d_brow,
                         c->n_brow, c->d_bcol, c->n_bcol, c->d_brow_first, c->d_brow_count, c->d_bcol_first,
                         c->d_bcol_count, c->d_bstate, c->d_bpart, c->d_bacc, c->d_bactive, c->mp,
-                        c->eps * c->opts.aca_eps_factor, c->plan.kcap, c->d_status, c->stream));
+                        c->eps * c->opts.aca_eps_factor, c->plan.kcap, cap_ok, c->d_status, c->stream));
   r = run_stages(c, c->plan.recomp_stages);
   if (r) return r;
   r = check_status(c, false);
+  if (r) {
+    c->ms_asm = now_ms() - t0;
+    return r;
+  }
+  c->kept_valid = false;
+  if (c->keep) {
+    // C~ for products after the factorisation (H-matvec, PCG, error norms)
+    const Plan& P = c->plan;
+    HIPCHK(c, hipMemcpyAsync(c->d_keep[0], c->d_buf[B_DENSE], P.dense_elems * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_keep[1], c->d_buf[B_U], P.u_elems * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_keep[2], c->d_buf[B_V], P.v_elems * 8, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_dyn_keep, c->d_dyn, (P.n_dyn + 1) * 4, hipMemcpyDeviceToDevice, c->stream));
+    c->kept_valid = true;
+  }
   c->ms_asm = now_ms() - t0;
-  if (r) return r;
   c->assembled = true;
   c->factored = false;
   return HCOV_OK;
 }
 
 // fixed-order sum of part[0..np) on the host after a device partial reduction
-int reduce_dev(hcov_ctx* c, const double* x, int64_t n, int mode, double* out) {
+int reduce_dev(hcov_ctx* c, const double* x, int64_t n, int mode, double* out, const double* y = nullptr) {
   int64_t np = 0;
-  HIPCHK(c, launch_reduce(x, n, mode, c->d_part, c->stream, &np));
+  HIPCHK(c, launch_reduce(x, y, n, mode, c->d_part, c->stream, &np));
   std::vector<double> h(np);
   if (np) HIPCHK(c, hipMemcpyAsync(h.data(), c->d_part, np * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -477,6 +501,11 @@ void hcov_opts_default(hcov_opts* o) {
   o->use_graphs = 1;
   o->oversample = 10;
   o->on_saturation = HCOV_SAT_RETRY;
+  o->keep_matrix = 0;
+  o->quad_mode = HCOV_QUAD_DIRECT;
+  o->pcg_tol = 1e-6;
+  o->pcg_max_iter = 150;
+  o->fixed_rank = 0;
 }
 
 const char* hcov_strerror(int code) {
@@ -500,6 +529,9 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   if (o.precision != HCOV_FP64 && o.precision != HCOV_MIXED) return HCOV_EINVAL;
   if (o.oversample < 2 || o.oversample > 64) return HCOV_EINVAL;
   if (o.on_saturation != HCOV_SAT_RETRY && o.on_saturation != HCOV_SAT_ERROR) return HCOV_EINVAL;
+  if (o.quad_mode != HCOV_QUAD_DIRECT && o.quad_mode != HCOV_QUAD_PCG) return HCOV_EINVAL;
+  if (!(o.pcg_tol > 0 && o.pcg_tol < 1) || o.pcg_max_iter < 1) return HCOV_EINVAL;
+  if (o.fixed_rank < 0 || o.fixed_rank > o.max_rank) return HCOV_EINVAL;
   std::vector<double> h(2 * n);
   for (int64_t i = 0; i < 2 * n; ++i) {
     if (!std::isfinite(locs[i])) return HCOV_EINVAL;
@@ -513,6 +545,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   c->eta = eta;
   c->eps = eps;
   c->opts = o;
+  c->keep = o.keep_matrix != 0 || o.quad_mode == HCOV_QUAD_PCG;
   c->stream = (hipStream_t)hip_stream;
   if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -605,6 +638,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   // memory estimate check
   size_t need = size_t(P.dense_elems + P.u_elems + P.v_elems + P.scr_elems + P.pers_elems + P.omega_rows * P.rcap +
                        2 * P.rhs_ld + P.linv_elems) * 8;
+  if (c->keep) need += size_t(P.dense_elems + P.u_elems + P.v_elems + 6 * n) * 8;
   if (o.mem_cap_bytes && need > o.mem_cap_bytes) {
     c->err = "estimate " + std::to_string(need) + " bytes exceeds the memory cap";
     return bail(HCOV_ENOMEM);
@@ -625,6 +659,14 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   c->d_tmp = (double*)dev_alloc(c, n * 8);
   for (int b = 0; b < B_COUNT; ++b)
     if (!c->d_buf[b]) return bail(HCOV_ENOMEM);
+  if (c->keep) {
+    c->d_keep[0] = (double*)dev_alloc(c, P.dense_elems * 8);
+    c->d_keep[1] = (double*)dev_alloc(c, P.u_elems * 8);
+    c->d_keep[2] = (double*)dev_alloc(c, P.v_elems * 8);
+    c->d_dyn_keep = (int*)dev_alloc(c, (P.n_dyn + 1) * 4);
+    c->d_vec = (double*)dev_alloc(c, 6 * n * 8);
+    if (!c->d_keep[0] || !c->d_keep[1] || !c->d_keep[2] || !c->d_dyn_keep || !c->d_vec) return bail(HCOV_ENOMEM);
+  }
   if (!c->d_dyn || !c->d_status || !c->d_logdet || !c->d_part || !c->d_tmp) return bail(HCOV_ENOMEM);
   hipMemsetAsync(c->d_dyn, 0, (P.n_dyn + 1) * 4, c->stream);
   // fixed Gaussian test matrix of the randomised range finder
@@ -702,6 +744,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   L.n_copy = int(cp.size());
   L.rmax = P.rmax;
   L.oversample = o.oversample;
+  L.fixed_rank = o.fixed_rank;
   // FP32 accumulation leaves noise of order 1e-7 relative in the low-rank
   // products: in mixed precision the truncations keep singular values above
   // max(eps, 1e-6) of the largest, so that noise is not kept as rank
@@ -712,6 +755,17 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   if (!L.dbufs || !L.gjobs || !L.gprods || !L.gtiles || !L.tsegs || !L.treds || !L.smalls || !L.leafs ||
       !L.trsms || !L.copy_pairs || !c->d_fill || !c->d_aca)
     return bail(HCOV_ENOMEM);
+  if (c->keep) {
+    // the launch context of the kept C~: its own arenas and dimensions
+    c->Lc = L;
+    c->Lc.bufs.p[B_DENSE] = c->d_keep[0];
+    c->Lc.bufs.p[B_U] = c->d_keep[1];
+    c->Lc.bufs.p[B_V] = c->d_keep[2];
+    std::vector<Bufs> kt(1, c->Lc.bufs);
+    c->Lc.dbufs = upload(c, kt);
+    c->Lc.dyn = c->d_dyn_keep;
+    if (!c->Lc.dbufs) return bail(HCOV_ENOMEM);
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(HCOV_EDEVICE);
   int r = assemble(c);
   if (r != HCOV_OK && r != HCOV_ERANK) {
@@ -804,19 +858,117 @@ int hcov_sample(hcov_ctx* c, const double* xi, double* y, int where) {
 
 int hcov_matvec(hcov_ctx* c, const double* x, double* y, int where) {
   if (!c || !x || !y) return HCOV_EINVAL;
-  if (!c->assembled) return fail(c, HCOV_ESTATE, "matvec needs the assembled (unfactored) matrix");
+  if (!c->assembled && !c->kept_valid)
+    return fail(c, HCOV_ESTATE, "matvec needs the assembled matrix (or opts.keep_matrix after a factorisation)");
   int r = to_cluster(c, x, where, c->d_buf[B_RHS]);
   if (r) return r;
-  r = run_stages(c, c->plan.matvec_stages);
+  r = run_stages(c, c->plan.matvec_stages, c->assembled ? nullptr : &c->Lc);
   if (r) return r;
   return from_cluster(c, c->d_buf[B_RHS] + c->plan.rhs_ld, y, where);
+}
+
+// ---------------------------------------------------------------- products on
+// device vectors in cluster order (n doubles each), through the B_RHS columns
+
+static int d2d(hcov_ctx* c, double* dst, const double* src) {
+  HIPCHK(c, hipMemcpyAsync(dst, src, c->n * 8, hipMemcpyDeviceToDevice, c->stream));
+  return HCOV_OK;
+}
+
+// y = C~ x: the assembled matrix, or its kept copy after a factorisation
+static int apply_C(hcov_ctx* c, const double* x, double* y) {
+  if (!c->assembled && !c->kept_valid) return fail(c, HCOV_ESTATE, "C~ is neither assembled nor kept");
+  int r = d2d(c, c->d_buf[B_RHS], x);
+  if (!r) r = run_stages(c, c->plan.matvec_stages, c->assembled ? nullptr : &c->Lc);
+  if (!r) r = d2d(c, y, c->d_buf[B_RHS] + c->plan.rhs_ld);
+  return r;
+}
+
+// y = (L~ L~^T)^{-1} x by the forward and backward H-triangular solves
+static int apply_Minv(hcov_ctx* c, const double* x, double* y) {
+  int r = d2d(c, c->d_buf[B_RHS], x);
+  if (!r) r = fwd_sweep(c);
+  for (size_t i = 0; !r && i < c->plan.bsolve_steps.size(); ++i) r = run_stages(c, c->plan.bsolve_steps[i]);
+  if (!r) r = d2d(c, y, c->d_buf[B_RHS]);
+  return r;
+}
+
+// y = L~ L~^T x
+static int apply_M(hcov_ctx* c, const double* x, double* y) {
+  double* col0 = c->d_buf[B_RHS];
+  double* col1 = col0 + c->plan.rhs_ld;
+  int r = d2d(c, col0, x);
+  if (!r) r = run_stages(c, c->plan.ltmul_stages);
+  if (!r) r = d2d(c, col0, col1);
+  if (!r) r = run_stages(c, c->plan.lmul_stages);
+  if (!r) r = d2d(c, y, col1);
+  return r;
+}
+
+static int dot(hcov_ctx* c, const double* x, const double* y, double* out) {
+  return reduce_dev(c, x, c->n, 2, out, y);
+}
+
+static int axpby(hcov_ctx* c, double* y, const double* x, double a, double b) {
+  HIPCHK(c, launch_axpby(y, x, a, b, c->n, c->stream));
+  return HCOV_OK;
+}
+
+// q = b^T C~^{-1} b by conjugate gradients on the kept C~ with the H-Cholesky
+// factor as preconditioner (the listing of Appendix B evaluates the quadratic
+// form by CG with the factor, 150 iterations, tolerance 1e-6), started from
+// the preconditioner's solution.  b: device, cluster order.
+static int pcg_quad(hcov_ctx* c, const double* b, double* quad) {
+  const int64_t n = c->n;
+  double* x = c->d_vec;
+  double* rr = x + n;
+  double* z = rr + n;
+  double* p = z + n;
+  double* w = p + n;
+  double bb = 0.0, rn2 = 0.0, rz = 0.0, rz_old = 1.0, pw = 0.0;
+  int r = apply_Minv(c, b, x);
+  if (!r) r = apply_C(c, x, w);
+  if (!r) r = d2d(c, rr, b);
+  if (!r) r = axpby(c, rr, w, -1.0, 1.0);
+  if (!r) r = dot(c, b, b, &bb);
+  if (r) return r;
+  int it = 0;
+  for (;; ++it) {
+    r = dot(c, rr, rr, &rn2);
+    if (r) return r;
+    if (!(rn2 > c->opts.pcg_tol * c->opts.pcg_tol * bb) || it >= c->opts.pcg_max_iter) break;
+    r = apply_Minv(c, rr, z);
+    if (!r) r = dot(c, rr, z, &rz);
+    if (!r) r = it == 0 ? d2d(c, p, z) : axpby(c, p, z, 1.0, rz / rz_old);
+    if (!r) r = apply_C(c, p, w);
+    if (!r) r = dot(c, p, w, &pw);
+    if (r) return r;
+    if (!(pw > 0.0) || !std::isfinite(pw)) return fail(c, HCOV_ENOTSPD, "CG: C~ is not positive definite");
+    const double alpha = rz / pw;
+    r = axpby(c, x, p, alpha, 1.0);
+    if (!r) r = axpby(c, rr, w, -alpha, 1.0);
+    if (r) return r;
+    rz_old = rz;
+  }
+  c->pcg_iters = it;
+  c->pcg_relres = bb > 0 ? std::sqrt(rn2 / bb) : 0.0;
+  return dot(c, b, x, quad);
 }
 
 int hcov_loglik(hcov_ctx* c, const double* z, int where, double* out_ll, double* out_logdet, double* out_quad) {
   if (!c || !z || !out_ll) return HCOV_EINVAL;
   int r;
   double quad = 0, ld = 0;
-  if (!c->factored) {
+  if (c->opts.quad_mode == HCOV_QUAD_PCG) {
+    if (!c->factored) {
+      r = factorise(c, nullptr, where);
+      if (r) return r;
+    }
+    double* b = c->d_vec + 5 * c->n;
+    r = to_cluster(c, z, where, b);
+    if (!r) r = pcg_quad(c, b, &quad);
+    if (r) return r;
+  } else if (!c->factored) {
     if (c->opts.fuse_solve) {
       r = factorise(c, z, where);
       if (r) return r;
@@ -841,6 +993,132 @@ int hcov_loglik(hcov_ctx* c, const double* z, int where, double* out_ll, double*
   return HCOV_OK;
 }
 
+int hcov_factor_matvec(hcov_ctx* c, const double* x, double* y, int where) {
+  if (!c || !x || !y) return HCOV_EINVAL;
+  if (!c->factored) return fail(c, HCOV_ESTATE, "L~ L~^T x requires hcov_cholesky");
+  if (!c->keep) return fail(c, HCOV_ESTATE, "L~ L~^T x needs opts.keep_matrix (vector workspace)");
+  double* b = c->d_vec + 5 * c->n;
+  int r = to_cluster(c, x, where, b);
+  if (!r) r = apply_M(c, b, c->d_vec);
+  if (!r) r = from_cluster(c, c->d_vec, y, where);
+  return r;
+}
+
+int hcov_error_norms(hcov_ctx* c, int iters, uint64_t seed, double* norm_c, double* err_fact, double* err_inv) {
+  if (!c || iters < 1) return HCOV_EINVAL;
+  if (!c->factored || !c->kept_valid)
+    return fail(c, HCOV_ESTATE, "error norms need a factorised context with opts.keep_matrix");
+  const int64_t n = c->n;
+  double* v = c->d_vec;
+  double* w = v + n;
+  double* u = w + n;
+  double* t = u + n;
+  int r = HCOV_OK;
+  // one power iteration: v <- op(v) / ||op(v)||, returns ||op(v)|| for unit v
+  auto power = [&](int which, uint64_t sd, double* est) -> int {
+    HIPCHK(c, launch_gaussian(v, n, sd, c->stream));
+    double nv = 0.0;
+    int rc = dot(c, v, v, &nv);
+    if (rc) return rc;
+    rc = axpby(c, v, v, 0.0, 1.0 / std::sqrt(nv));
+    double lam = 0.0;
+    for (int k = 0; !rc && k < iters; ++k) {
+      if (which == 0) {                      // C~ v
+        rc = apply_C(c, v, w);
+      } else if (which == 1) {               // (C~ - L~L~^T) v
+        rc = apply_C(c, v, w);
+        if (!rc) rc = apply_M(c, v, u);
+        if (!rc) rc = axpby(c, w, u, -1.0, 1.0);
+      } else {                               // A^T A v, A = I - (L~L~^T)^{-1} C~
+        rc = apply_C(c, v, t);
+        if (!rc) rc = apply_Minv(c, t, u);
+        if (!rc) rc = axpby(c, u, v, 1.0, -1.0);   // u = A v
+        if (!rc) rc = dot(c, u, u, &lam);          // ||A v||^2
+        if (!rc) rc = apply_Minv(c, u, t);
+        if (!rc) rc = apply_C(c, t, w);
+        if (!rc) rc = axpby(c, w, u, 1.0, -1.0);   // w = A^T u
+      }
+      double nw = 0.0;
+      if (!rc) rc = dot(c, w, w, &nw);
+      if (rc) break;
+      if (which != 2) lam = nw;
+      if (!(nw > 0.0)) break;
+      rc = axpby(c, v, w, 1.0 / std::sqrt(nw), 0.0);
+    }
+    *est = std::sqrt(lam);
+    return rc;
+  };
+  double e0 = 0, e1 = 0, e2 = 0;
+  r = power(0, seed, &e0);
+  if (!r) r = power(1, seed + 1, &e1);
+  if (!r) r = power(2, seed + 2, &e2);
+  if (r) return r;
+  if (norm_c) *norm_c = e0;
+  if (err_fact) *err_fact = e1;
+  if (err_inv) *err_inv = e2;
+  return HCOV_OK;
+}
+
+int hcov_exact_matvec(hcov_ctx* c, const double* x, double* y, int where) {
+  if (!c || !x || !y) return HCOV_EINVAL;
+  int r = to_cluster(c, x, where, c->d_buf[B_RHS]);
+  if (r) return r;
+  HIPCHK(c, launch_exact_matvec(c->d_loc, c->d_buf[B_RHS], c->d_buf[B_RHS] + c->plan.rhs_ld, c->n, c->mp,
+                                c->stream));
+  return from_cluster(c, c->d_buf[B_RHS] + c->plan.rhs_ld, y, where);
+}
+
+int hcov_exact_norms(hcov_ctx* c, int iters, uint64_t seed, double* err_c, double* err_cinv) {
+  if (!c || iters < 1) return HCOV_EINVAL;
+  if (!c->factored || !c->kept_valid)
+    return fail(c, HCOV_ESTATE, "exact error norms need a factorised context with opts.keep_matrix");
+  const int64_t n = c->n;
+  double* v = c->d_vec;
+  double* w = v + n;
+  double* u = w + n;
+  double* t = u + n;
+  auto exact = [&](const double* a, double* b) -> int {
+    HIPCHK(c, launch_exact_matvec(c->d_loc, a, b, n, c->mp, c->stream));
+    return HCOV_OK;
+  };
+  auto power = [&](int which, uint64_t sd, double* est) -> int {
+    HIPCHK(c, launch_gaussian(v, n, sd, c->stream));
+    double nv = 0.0, lam = 0.0;
+    int rc = dot(c, v, v, &nv);
+    if (!rc) rc = axpby(c, v, v, 0.0, 1.0 / std::sqrt(nv));
+    for (int k = 0; !rc && k < iters; ++k) {
+      if (which == 0) {                      // (C - C~) v
+        rc = exact(v, w);
+        if (!rc) rc = apply_C(c, v, u);
+        if (!rc) rc = axpby(c, w, u, -1.0, 1.0);
+      } else {                               // B^T B v, B = C (L~L~^T)^{-1} - I
+        rc = apply_Minv(c, v, t);
+        if (!rc) rc = exact(t, u);
+        if (!rc) rc = axpby(c, u, v, -1.0, 1.0);   // u = B v
+        if (!rc) rc = dot(c, u, u, &lam);
+        if (!rc) rc = exact(u, t);
+        if (!rc) rc = apply_Minv(c, t, w);
+        if (!rc) rc = axpby(c, w, u, -1.0, 1.0);   // w = B^T u
+      }
+      double nw = 0.0;
+      if (!rc) rc = dot(c, w, w, &nw);
+      if (rc) break;
+      if (which == 0) lam = nw;
+      if (!(nw > 0.0)) break;
+      rc = axpby(c, v, w, 1.0 / std::sqrt(nw), 0.0);
+    }
+    *est = std::sqrt(lam);
+    return rc;
+  };
+  double e0 = 0, e1 = 0;
+  int r = power(0, seed, &e0);
+  if (!r) r = power(1, seed + 1, &e1);
+  if (r) return r;
+  if (err_c) *err_c = e0;
+  if (err_cinv) *err_cinv = e1;
+  return HCOV_OK;
+}
+
 int hcov_stats(const hcov_ctx* c, hcov_stats_t* s) {
   if (!c || !s) return HCOV_EINVAL;
   std::memset(s, 0, sizeof(*s));
@@ -862,6 +1140,8 @@ int hcov_stats(const hcov_ctx* c, hcov_stats_t* s) {
   s->n_graph_replays = c->n_replays;
   s->n_sketch_retries = c->n_retries;
   s->sketch_saturated = c->sat_last;
+  s->pcg_iters = c->pcg_iters;
+  s->pcg_relres = c->pcg_relres;
   // ranks
   std::vector<int> dyn(P.n_dyn + 1);
   if (hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||

@@ -1478,7 +1478,8 @@ __device__ __forceinline__ void sketch_report(const SmallJob& J, int* __restrict
 //   SK_SKETCH_F SVD of A = R1 R2^{-1}: C1 = R2^{-1} Y_k, k = #{s > eps s_1}
 __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, int* __restrict__ dyn,
                                                const SmallJob* __restrict__ jobs, int j0, int rmax,
-                                               double eps_run, double tau_run, int* __restrict__ status) {
+                                               double eps_run, double tau_run, int fixed_rank,
+                                               int* __restrict__ status) {
   const SmallJob J = jobs[j0 + blockIdx.x];
   const int n = dimv(dyn, J.k);
   extern __shared__ double smem[];
@@ -1684,6 +1685,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
       } else if (!isfinite(smax) && lane == 0) {
         atomicOr(status, STAT_NONFINITE);
       }
+      if (fixed_rank > 0) kk = min(kk, fixed_rank);
       if (kk > J.cap) {
         if (lane == 0) atomicOr(status, STAT_RANK_OVERFLOW);
         kk = J.cap;
@@ -1783,6 +1785,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
   } else if (!isfinite(smax)) {
     if (tid == 0) atomicOr(status, STAT_NONFINITE);
   }
+  if (fixed_rank > 0) kk = min(kk, fixed_rank);
   if (kk > J.cap) {
     if (tid == 0) atomicOr(status, STAT_RANK_OVERFLOW);
     kk = J.cap;
@@ -2330,7 +2333,7 @@ __device__ double block_sum(double v, double* s8) {
 __global__ __launch_bounds__(256) void k_aca(double* __restrict__ Ub, double* __restrict__ Vb,
                                              int* __restrict__ dyn, const double2* __restrict__ loc,
                                              const AcaJob* __restrict__ jobs, MaternParams P,
-                                             double eps_aca, int kcap, int* __restrict__ status) {
+                                             double eps_aca, int kcap, int cap_ok, int* __restrict__ status) {
   const AcaJob J = jobs[blockIdx.x];
   double* __restrict__ U = Ub + J.off_u;
   double* __restrict__ V = Vb + J.off_v;
@@ -2448,7 +2451,7 @@ __global__ __launch_bounds__(256) void k_aca(double* __restrict__ Ub, double* __
     }
     i = ni;
   }
-  if (k == kmax && kmax < min(p, q) && tid == 0) atomicOr(status, STAT_RANK_OVERFLOW);
+  if (k == kmax && kmax < min(p, q) && !cap_ok && tid == 0) atomicOr(status, STAT_RANK_OVERFLOW);
   if (tid == 0) dyn[J.rank_slot] = k;
   (void)dots;
 }
@@ -2486,8 +2489,10 @@ __global__ void k_permute(const double* __restrict__ in, double* __restrict__ ou
 // Fixed-order FP64 reduction: partial sums of x[i]^2 (mode 0) or x[i]
 // (mode 1) per block of 1024, written to part[]; the host (or a second
 // launch with one block) finishes in block order.
-__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ x, int64_t n, int mode,
-                                                double* __restrict__ part) {
+// Partial sums of 1024 entries per work-group: mode 0 sum x_i^2, mode 1
+// sum x_i, mode 2 sum x_i y_i (fixed order: deterministic).
+__global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ x, const double* __restrict__ y,
+                                                int64_t n, int mode, double* __restrict__ part) {
   __shared__ double s8[8];
   int64_t base = (int64_t)blockIdx.x * 1024;
   double s = 0.0;
@@ -2495,7 +2500,7 @@ __global__ __launch_bounds__(256) void k_reduce(const double* __restrict__ x, in
     int64_t i = base + threadIdx.x + 256 * r;
     if (i < n) {
       double v = x[i];
-      s += mode == 0 ? v * v : v;
+      s += mode == 0 ? v * v : (mode == 1 ? v : v * y[i]);
     }
   }
   s = block_sum(s, s8);
@@ -2508,6 +2513,37 @@ __global__ void k_matern_probe(const double* __restrict__ h, double* __restrict_
   if (i < n) out[i] = matern_eval(h[i], P);
 }
 
+
+// y = C x with the exact entries of Eq. (3) evaluated on the fly (plus the
+// nugget on the diagonal): one row per thread, the columns streamed through
+// LDS in tiles of 256 locations, summed in increasing column order.
+__global__ __launch_bounds__(256) void k_exact_matvec(const double2* __restrict__ loc, const double* __restrict__ x,
+                                                      double* __restrict__ y, int64_t n, MaternParams P) {
+  __shared__ double2 sl[256];
+  __shared__ double sx[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const double2 me = i < n ? loc[i] : make_double2(0.0, 0.0);
+  double acc = 0.0;
+  for (int64_t j0 = 0; j0 < n; j0 += 256) {
+    const int64_t j = j0 + threadIdx.x;
+    sl[threadIdx.x] = j < n ? loc[j] : make_double2(0.0, 0.0);
+    sx[threadIdx.x] = j < n ? x[j] : 0.0;
+    __syncthreads();
+    const int m = (int)min<int64_t>(256, n - j0);
+    for (int t = 0; t < m; ++t) {
+      const double dx = me.x - sl[t].x, dy = me.y - sl[t].y;
+      acc = fma(matern_eval(sqrt(dx * dx + dy * dy), P), sx[t], acc);
+    }
+    __syncthreads();
+  }
+  if (i < n) y[i] = fma(P.nugget, x[i], acc);
+}
+
+hipError_t launch_exact_matvec(const double* loc, const double* x, double* y, int64_t n, const MaternParams& P,
+                               hipStream_t st) {
+  if (n > 0) k_exact_matvec<<<(unsigned)((n + 255) / 256), 256, 0, st>>>((const double2*)loc, x, y, n, P);
+  return hipGetLastError();
+}
 
 // counter-based standard normals: splitmix64 bits, Box-Muller pairs
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
@@ -2568,7 +2604,8 @@ hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st) {
       break;
     case ST_SMALL:
       if (n > 0)
-        k_small<<<n, 256, LDS_SMALL, st>>>(L.dbufs, L.dyn, L.smalls, s.begin, L.rmax, L.eps, L.tau, L.status);
+        k_small<<<n, 256, LDS_SMALL, st>>>(L.dbufs, L.dyn, L.smalls, s.begin, L.rmax, L.eps, L.tau, L.fixed_rank,
+                                           L.status);
       break;
     case ST_LEAF:
       if (n > 0) k_leaf<<<n, 256, LDS_LEAF, st>>>(L.dbufs, L.leafs, s.begin, L.logdet, L.status);
@@ -2601,8 +2638,9 @@ hipError_t launch_fill(double* D, const double* loc, const FillJob* jobs, int nj
 }
 
 hipError_t launch_aca(double* U, double* V, int* dyn, const double* loc, const AcaJob* jobs, int njobs,
-                      const MaternParams& P, double eps_aca, int kcap, int* status, hipStream_t st) {
-  if (njobs > 0) k_aca<<<njobs, 256, 0, st>>>(U, V, dyn, (const double2*)loc, jobs, P, eps_aca, kcap, status);
+                      const MaternParams& P, double eps_aca, int kcap, int cap_ok, int* status, hipStream_t st) {
+  if (njobs > 0)
+    k_aca<<<njobs, 256, 0, st>>>(U, V, dyn, (const double2*)loc, jobs, P, eps_aca, kcap, cap_ok, status);
   return hipGetLastError();
 }
 
@@ -2612,10 +2650,22 @@ hipError_t launch_permute(const double* in, double* out, const int* perm, int64_
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(const double* x, int64_t n, int mode, double* part, hipStream_t st, int64_t* nparts) {
+hipError_t launch_reduce(const double* x, const double* y, int64_t n, int mode, double* part, hipStream_t st,
+                         int64_t* nparts) {
   int64_t nb = (n + 1023) / 1024;
   *nparts = nb;
-  if (nb > 0) k_reduce<<<(unsigned)nb, 256, 0, st>>>(x, n, mode, part);
+  if (nb > 0) k_reduce<<<(unsigned)nb, 256, 0, st>>>(x, y, n, mode, part);
+  return hipGetLastError();
+}
+
+// y = a x + b y
+__global__ void k_axpby(double* __restrict__ y, const double* __restrict__ x, double a, double b, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = fma(a, x[i], b * y[i]);
+}
+
+hipError_t launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t st) {
+  if (n > 0) k_axpby<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(y, x, a, b, n);
   return hipGetLastError();
 }
 

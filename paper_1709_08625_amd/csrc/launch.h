@@ -40,6 +40,7 @@ struct LaunchCtx {
   int n_copy;
   int rmax;
   int oversample;       // sketch columns beyond the assembly rank (ST_COPY_RANK)
+  int fixed_rank;       // > 0: every truncation keeps at most this rank
   double eps;
   double tau;
   double* logdet;
@@ -59,7 +60,7 @@ hipError_t run_aca_big(double* U, double* V, int* dyn, const double* loc, const 
                        const AcaBigChunk* d_rows, int nrow, const AcaBigChunk* d_cols, int ncol,
                        const int* d_row_first, const int* d_row_count, const int* d_col_first,
                        const int* d_col_count, AcaBigState* d_state, double* d_part, double* d_acc,
-                       int* d_active, const MaternParams& P, double eps_aca, int kcap, int* status,
+                       int* d_active, const MaternParams& P, double eps_aca, int kcap, int cap_ok, int* status,
                        hipStream_t st);
 
 hipError_t setup_kernel_attributes();
@@ -67,12 +68,16 @@ hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st);
 hipError_t launch_adopt_hints(const LaunchCtx& L, hipStream_t st);
 hipError_t launch_fill(double* D, const double* loc, const FillJob* jobs, int njobs,
                        const MaternParams& P, hipStream_t st);
+// cap_ok: reaching the rank capacity is not an error (fixed-rank mode)
 hipError_t launch_aca(double* U, double* V, int* dyn, const double* loc, const AcaJob* jobs, int njobs,
-                      const MaternParams& P, double eps_aca, int kcap, int* status, hipStream_t st);
+                      const MaternParams& P, double eps_aca, int kcap, int cap_ok, int* status, hipStream_t st);
 hipError_t launch_permute(const double* in, double* out, const int* perm, int64_t n, int scatter,
                           hipStream_t st);
-hipError_t launch_reduce(const double* x, int64_t n, int mode, double* part, hipStream_t st,
+hipError_t launch_reduce(const double* x, const double* y, int64_t n, int mode, double* part, hipStream_t st,
                          int64_t* nparts);
+hipError_t launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t st);
+hipError_t launch_exact_matvec(const double* loc, const double* x, double* y, int64_t n, const MaternParams& P,
+                               hipStream_t st);
 hipError_t launch_probe(const double* h, double* out, int64_t n, const MaternParams& P, hipStream_t st);
 hipError_t launch_gaussian(double* out, int64_t n, uint64_t seed, hipStream_t st);
 hipError_t launch_fill_value(double* out, int64_t n, double v, hipStream_t st);

@@ -1143,14 +1143,14 @@ void Builder::build_solves() {
   }
 }
 
-// y = C~ x on the assembled matrix (x = B_RHS col 0, y = col 1), and
-// y = L~ x on the factor.  Output rows are split by leaf cluster so every
-// job owns its rows.
+// y = C~ x on the assembled matrix (x = B_RHS col 0, y = col 1), y = L~ x
+// and y = L~^T x on the factor.  Output rows are split by leaf cluster so
+// every job owns its rows.
 void Builder::build_matvec() {
   const int D = P.D;
   const int64_t m = int64_t(1) << D;
-  for (int pass = 0; pass < 2; ++pass) {
-    std::vector<Stage>& out = pass == 0 ? P.matvec_stages : P.lmul_stages;
+  for (int pass = 0; pass < 3; ++pass) {
+    std::vector<Stage>& out = pass == 0 ? P.matvec_stages : (pass == 1 ? P.lmul_stages : P.ltmul_stages);
     scr_top = 0;
     Ref X{B_RHS, int32_t(P.rhs_ld), 0};
     std::vector<int32_t> jobB(m);
@@ -1172,7 +1172,8 @@ void Builder::build_matvec() {
       };
       bool diag = (B.a == B.c);
       for (int side = 0; side < 2; ++side) {
-        if (side == 1 && diag) break;   // diagonal tiles hold both triangles (C) / lower (L)
+        if (pass == 2 && side == 0) continue;   // L^T x: the transposed lower part only
+        if (side == 1 && diag && pass != 2) break;   // diagonal tiles hold both triangles (C) / lower (L)
         if (side == 1 && pass == 1) break;   // L x uses the lower part only
         // side 0: y[rows] += M x[cols]; side 1: y[cols] += M^T x[rows]
         int64_t o0 = side == 0 ? B.r0 : B.c0, o1 = side == 0 ? B.r1 : B.c1;

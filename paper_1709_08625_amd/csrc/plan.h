@@ -198,8 +198,9 @@ struct Plan {
   std::vector<std::vector<Stage>> bsolve_steps;
   // H-matvec C~ x (assembled matrix), x in B_RHS col 0, y in col 1
   std::vector<Stage> matvec_stages;
-  // y = L~ x (x in B_RHS col 0, y col 1)
+  // y = L~ x and y = L~^T x (x in B_RHS col 0, y col 1)
   std::vector<Stage> lmul_stages;
+  std::vector<Stage> ltmul_stages;
 
   int64_t rhs_ld = 0;   // leading dimension of B_RHS (= n), 2 columns
 

@@ -16,6 +16,7 @@ OK, EINVAL, ENOTSPD, ENOMEM, ESTATE, EDEVICE, ERANK = 0, -1, -2, -3, -4, -5, -6
 HOST, DEVICE = 0, 1
 FP64, MIXED = 0, 1
 SAT_RETRY, SAT_ERROR = 0, 1
+QUAD_DIRECT, QUAD_PCG = 0, 1
 
 
 class Theta(C.Structure):
@@ -41,7 +42,8 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("max_rank", C.c_int), ("aca_eps_factor", C.c_double),
                 ("fuse_solve", C.c_int), ("mem_cap_bytes", C.c_size_t), ("alloc", ALLOC_FN),
                 ("free", FREE_FN), ("alloc_user", C.c_void_p), ("use_graphs", C.c_int),
-                ("oversample", C.c_int), ("on_saturation", C.c_int)]
+                ("oversample", C.c_int), ("on_saturation", C.c_int), ("keep_matrix", C.c_int),
+                ("quad_mode", C.c_int), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int), ("fixed_rank", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -51,7 +53,8 @@ class Stats(C.Structure):
                 ("bytes_factor", C.c_int64), ("ms_tree", C.c_double), ("ms_assemble", C.c_double),
                 ("ms_factor", C.c_double), ("ms_solve", C.c_double), ("n_steps", C.c_int64),
                 ("n_launches_factor", C.c_int64), ("n_graph_replays", C.c_int64),
-                ("n_sketch_retries", C.c_int64), ("sketch_saturated", C.c_int), ("mean_sketch_width", C.c_double)]
+                ("n_sketch_retries", C.c_int64), ("sketch_saturated", C.c_int), ("mean_sketch_width", C.c_double),
+                ("pcg_iters", C.c_int), ("pcg_relres", C.c_double)]
 
 
 _lib = None
@@ -75,6 +78,10 @@ def lib():
         L.hcov_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, dp, C.c_int]
         L.hcov_sample.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.hcov_matvec.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.hcov_factor_matvec.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.hcov_error_norms.argtypes = [C.c_void_p, C.c_int, C.c_uint64, dp, dp, dp]
+        L.hcov_exact_matvec.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.hcov_exact_norms.argtypes = [C.c_void_p, C.c_int, C.c_uint64, dp, dp]
         L.hcov_loglik.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, dp]
         L.hcov_stats.argtypes = [C.c_void_p, C.POINTER(Stats)]
         L.hcov_estimate_bytes.argtypes = [dp, C.c_int64, C.c_double, C.c_int, C.c_double, C.POINTER(Opts),
@@ -307,6 +314,32 @@ class HCov:
         y = np.empty(self.n)
         self._chk(lib().hcov_matvec(self._ctx, C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data), HOST))
         return y
+
+    def factor_matvec(self, x):
+        """L~ L~^T x (needs opts keep_matrix)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.empty(self.n)
+        self._chk(lib().hcov_factor_matvec(self._ctx, C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data), HOST))
+        return y
+
+    def error_norms(self, iters=30, seed=1):
+        """(||C~||_2, ||C~ - L~L~^T||_2, ||I - (L~L~^T)^{-1} C~||_2) by power iteration."""
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        self._chk(lib().hcov_error_norms(self._ctx, int(iters), C.c_uint64(seed), C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def exact_matvec(self, x):
+        """C x with the exact Matérn entries (device, on the fly)."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        y = np.empty(self.n)
+        self._chk(lib().hcov_exact_matvec(self._ctx, C.c_void_p(x.ctypes.data), C.c_void_p(y.ctypes.data), HOST))
+        return y
+
+    def exact_norms(self, iters=30, seed=1):
+        """(||C - C~||_2, ||C (L~L~^T)^{-1} - I||_2) by power iteration."""
+        a, b = C.c_double(), C.c_double()
+        self._chk(lib().hcov_exact_norms(self._ctx, int(iters), C.c_uint64(seed), C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def stats(self):
         s = Stats()

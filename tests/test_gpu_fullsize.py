@@ -50,3 +50,54 @@ def test_full_size_matvec_rows_and_sweep_properties():
         assert h.loglik(z) == (ll, ld, q)
     finally:
         h.close()
+
+
+def test_full_size_factor_residual():
+    # the factorisation's own accuracy at the benchmark's size: with the kept
+    # C~, ||C~ x - L~ L~^T x|| / ||C~ x|| for a random x (an H-Cholesky at block
+    # accuracy eps leaves a residual of order eps times the block-tree's
+    # sparsity and depth; asserted at 100 eps) and the back-solve
+    # ||(L~L~^T)^{-1} C~ x - x|| / ||x|| (Table 5's error measure, applied to x)
+    from paper_1709_08625_amd import hcov
+    locs, _ = workloads.uniform(N, seed=0)
+    h = hcov.HCov(locs, THETA, eps=1e-7, leaf=128, eta=2.0, opts={"keep_matrix": 1})
+    try:
+        x = np.random.default_rng(21).standard_normal(N)
+        y = h.matvec(x)
+        h.cholesky()
+        assert np.array_equal(h.matvec(x), y)
+        m = h.factor_matvec(x)
+        res = float(np.linalg.norm(y - m) / np.linalg.norm(y))
+        back = h.solve(y)
+        berr = float(np.linalg.norm(back - x) / np.linalg.norm(x))
+        print(f"n={N}: ||C~x - L~L~'x||/||C~x|| = {res:.2e}, ||(L~L~')^-1 C~x - x||/||x|| = {berr:.2e}")
+        assert res < 1e-5
+        assert berr < 1e-1
+    finally:
+        h.close()
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.5])
+def test_line_kalman_exact_at_half_million(nu):
+    # points on a line with a nugget: the Matérn field restricted to the line
+    # is a Gauss-Markov process (a 1- or 2-dimensional state), so the Kalman
+    # filter's prediction-error decomposition gives Eq. (1) exactly in O(n)
+    # (oracle.markov.kalman_loglik); z is white noise (the hardest right-hand
+    # side for the factor), held to the FP64 tolerance 1e-6 of S
+    from oracle import markov
+    from paper_1709_08625_amd import hcov
+    n = 524288
+    locs, xi = workloads.line(n, seed=17)
+    th = (1.3, 0.01, nu, 1e-4)
+    ll0, ld0, q0 = markov.kalman_loglik(locs[:, 0], xi, *th)
+    h = hcov.HCov(locs, th, eps=1e-9, leaf=128, eta=2.0)
+    try:
+        ll, ld, q = h.loglik(xi)
+        S = 0.5 * n * np.log(2 * np.pi) + abs(ld0) / 2 + q0 / 2
+        print(f"line n={n} nu={nu}: |dL|/S {abs(ll - ll0) / S:.2e} logdet {abs(ld - ld0) / S:.2e} "
+              f"q {abs(q - q0) / S:.2e} maxrank {h.stats()['max_rank_seen']}")
+        assert abs(ll - ll0) / S < 1e-6
+        assert abs(ld - ld0) / S < 1e-6
+        assert abs(q - q0) / S < 1e-6
+    finally:
+        h.close()

@@ -240,3 +240,25 @@ def test_config1_anchor_values():
     assert abs(ll - (-1127.57885049644)) < 2e-9 * 1127.6
     # and q = ||xi||^2 exactly up to rounding when Z = L xi
     assert abs(q - float(xi @ xi)) < 1e-9 * q
+
+
+def test_cov_block_tiles_cov_matrix():
+    # the block assembly used for the large dense fixtures is the same
+    # arithmetic as cov_matrix, entry for entry
+    locs, _ = workloads.uniform(300, seed=8)
+    th = (1.2, 0.09, 0.8)
+    C = dense.cov_matrix(locs, *th, 0.0)
+    B = np.vstack([dense.cov_block(locs[i:i + 64], locs, *th) for i in range(0, 300, 64)])
+    assert np.array_equal(B, C)
+
+
+def test_torch_lapack_path_matches_scipy():
+    # the MKL route used for the n = 32768 fixtures against the SciPy route
+    locs, xi = workloads.uniform(500, seed=9)
+    C = dense.cov_matrix(locs, 1.0, 0.1, 0.8, 1e-4)
+    L1 = dense.cholesky_lapack(C)
+    L2 = dense.cholesky_torch(C)
+    assert np.max(np.abs(L1 - L2)) < 1e-12 * np.max(np.abs(L1))
+    v1 = dense.forward_solve_lapack(L1, xi)
+    v2 = dense.forward_solve_torch(L2, xi)
+    assert np.max(np.abs(v1 - v2)) < 1e-9 * np.max(np.abs(v1))
