@@ -38,7 +38,11 @@ def _alone(locs, z, th, eps, leaf, eta):
 
 
 def test_mix_equals_alone():
-    eps, leaf, eta = 1e-8, 64, 2.0
+    # eps 1e-9, the block accuracy at which the FP64 tolerance 1e-6 of S is
+    # stated (these smooth kernels, nu up to 2.5 with ell up to 0.3 and nugget
+    # 1e-4, have condition numbers ~1e7; at eps 1e-8 one request lands at
+    # 1.03e-6)
+    eps, leaf, eta = 1e-9, 64, 2.0
     reqs = _requests(10, seed=3, model_z=True)
     alone = [_alone(l, z, th, eps, leaf, eta) for l, z, th in reqs]
     S = hcov.Server(slots=4)
