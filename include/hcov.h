@@ -197,7 +197,7 @@ int hcov_set_theta(hcov_ctx* ctx, hcov_theta theta);
  * of at least the width minus one while the sketch is narrower than the
  * block, the sketch is saturated and eps is no longer guaranteed for that
  * block.  After such a factorisation every block's rank hint becomes the
- * rank it kept, 1.5 times its sketch width plus 2 where the sketch
+ * rank it kept, its sketch width plus max(8, width / 4) where the sketch
  * saturated.  With
  * HCOV_SAT_RETRY the matrix is re-assembled and the factorisation redone
  * with the new widths, up to 4 times; a sketch saturated at the widest width

@@ -1335,66 +1335,101 @@ __device__ __forceinline__ void reg_set(double (&r)[RU], int j, double x) {
   for (int u = 0; u < RU; ++u) r[u] = (u == j) ? x : r[u];
 }
 
-// Second half for n <= 32 by the work-group: eight lanes per output column
-// c < kk, lane s holding rows s + 8 r (r < 4).  Z = Q2 V[:, ord[c]]
-// (reflectors applied last to first, each read as a broadcast, each dot
-// product reduced over the eight lanes with DPP moves), then
-// C1[:, c] = R2^{-1} Z[:, c] by back substitution, each new entry passed
-// along the eight lanes of its column by a lane permute.
+// Second half of the truncation by the work-group, G lanes per output column
+// c < kk (tid / G), lane s holding rows s + G r (r < R; G R = 32 for n <= 32,
+// 64 for n <= 64).  Z = Q2 V[:, ord[c]] (reflectors applied last to first,
+// each read as a broadcast, each dot product reduced over the G lanes with
+// DPP moves), then C1[:, c] = R2^{-1} Z[:, c] by back substitution, each new
+// entry passed along the G lanes of its column by a lane permute.
+template <int G, int R>
 __device__ void sketch_f_out_wg(const double* V, const double* R1, const double* R2, const double* beta,
                                 const int* ord, int n, int kk, double* __restrict__ C1, int rmax) {
-  const int tid = threadIdx.x, c = tid >> 3, s = tid & 7, lane = tid & 63;
+  constexpr int NR = G * R;
+  const int tid = threadIdx.x, c = tid / G, s = tid % G, lane = tid & 63;
   const bool act = c < kk;
   const int oc = act ? ord[c] : 0;
-  double z[4];
+  double z[R];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int u = s + 8 * r;
-    const double x = V[u + oc * SM];
+  for (int r = 0; r < R; ++r) {
+    const int u = s + G * r;
+    const double x = V[(u < n ? u : 0) + oc * SM];
     z[r] = (act && u < n) ? x : 0.0;
   }
 #pragma unroll
-  for (int j = 31; j >= 0; --j) {
+  for (int j = NR - 1; j >= 0; --j) {
     if (j >= n) continue;
     const double bj = beta[j];
     const double v0 = beta[SM + j];
     const int base = j * n - j * (j + 1) / 2 - j - 1;   // packed reflector tail, rows > j
-    double cv[4];
+    double cv[R];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int u = s + 8 * r;
+    for (int r = 0; r < R; ++r) {
+      const int u = s + G * r;
       const bool tail = u > j && u < n;
       const double t = R1[tail ? base + u : 0];
       cv[r] = (u == j) ? v0 : (tail ? t : 0.0);
     }
     double d = cv[0] * z[0];
-    d = fma(cv[1], z[1], d);
-    d = fma(cv[2], z[2], d);
-    d = fma(cv[3], z[3], d);
-    d = group_sum<8>(d) * bj;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) z[r] = (bj != 0.0) ? fma(-d, cv[r], z[r]) : z[r];   // bj == 0: H_j = I
+    for (int r = 1; r < R; ++r) d = fma(cv[r], z[r], d);
+    d = group_sum<G>(d) * bj;
+#pragma unroll
+    for (int r = 0; r < R; ++r) z[r] = (bj != 0.0) ? fma(-d, cv[r], z[r]) : z[r];   // bj == 0: H_j = I
   }
 #pragma unroll
-  for (int i = 31; i >= 0; --i) {
+  for (int i = NR - 1; i >= 0; --i) {
     if (i >= n) continue;
     const double* col = R2 + i * (i + 1) / 2;   // packed upper column i
     const double dg = col[i];
-    double x = (dg != 0.0) ? z[i >> 3] / dg : 0.0;   // right on the lane holding row i
-    x = __shfl(x, (lane & ~7) | (i & 7));
+    double x = (dg != 0.0) ? z[i / G] / dg : 0.0;   // right on the lane holding row i
+    x = __shfl(x, (lane & ~(G - 1)) | (i % G));
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int u = s + 8 * r;
+    for (int r = 0; r < R; ++r) {
+      const int u = s + G * r;
       const double cu = col[u < i ? u : 0];
       z[r] = (u == i) ? x : ((u < i) ? fma(-cu, x, z[r]) : z[r]);
     }
   }
   if (act) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int u = s + 8 * r;
+    for (int r = 0; r < R; ++r) {
+      const int u = s + G * r;
       if (u < n) C1[u + (size_t)c * rmax] = z[r];
     }
+  }
+}
+
+// M = R1 R2^{-1} row by row with G lanes per row i (tid / G), lane s holding
+// the entries l = s + G r (r < R; G R >= n): entry j is the row's dot product
+// so far with column j of R2 (reduced over the G lanes by DPP), subtracted
+// from R1's entry and divided by the diagonal.
+template <int G, int R>
+__device__ void sketch_f_m_wg(const double* R1, const double* R2, int n, double* A) {
+  const int tid = threadIdx.x, i = tid / G, s = tid % G;
+  double g[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) g[r] = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double* col = R2 + j * (j + 1) / 2;   // column j of R2 (rows <= j)
+    double p = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int l = s + G * r;
+      const double c = col[l < j ? l : 0];
+      p = fma(l < j ? g[r] : 0.0, c, p);
+    }
+    p = group_sum<G>(p);
+    const double a = (i < n && i <= j) ? R1[upk(i, j)] : 0.0;
+    const double d = col[j];
+    const double gj = (d != 0.0) ? (a - p) / d : 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (j == s + G * r) g[r] = gj;
+  }
+  if (i < n) {
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (s + G * r < n) A[i + (s + G * r) * SM] = g[r];
   }
 }
 
@@ -1454,7 +1489,8 @@ __device__ __forceinline__ bool sketch_saturated(int kept, int r, int full) {
 
 // Truncation result of a sketched low-rank target (one thread): the kept rank
 // is the block's candidate rank hint for the next factorisation's sketch
-// width; a saturated sketch proposes 1.5 times its width plus 2 and raises
+// width; a saturated sketch proposes its width plus max(8, width / 4) (a
+// modest step: the kernels for widths up to 64 are much faster) and raises
 // STAT_SKETCH_SAT (and STAT_SAT_CAP when the sketch was already as wide as
 // the plan allows).
 __device__ __forceinline__ void sketch_report(const SmallJob& J, int* __restrict__ dyn, int kept,
@@ -1462,7 +1498,7 @@ __device__ __forceinline__ void sketch_report(const SmallJob& J, int* __restrict
   if (J.sat.maxv < 0) return;
   const int r = dimv(dyn, J.sat);
   const bool sat = sketch_saturated(kept, r, J.full);
-  if (J.cand_slot >= 0) dyn[J.cand_slot] = sat ? r + r / 2 + 2 : kept;
+  if (J.cand_slot >= 0) dyn[J.cand_slot] = sat ? r + max(8, r / 4) : kept;
   if (sat) {
     atomicOr(status, r >= J.sat.maxv ? (STAT_SKETCH_SAT | STAT_SAT_CAP) : STAT_SKETCH_SAT);
     atomicAdd(status + 2, 1);   // saturated blocks of this factorisation
@@ -1575,62 +1611,15 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     return;
   }
   if (J.kind == SK_SKETCH_F && n <= 64) {
-    // The truncation: eight lanes per row (n <= 32; else the first wave,
-    // lane = row) form M = R1 R2^{-1}; the
-    // work-group forms M^T = Q2 R2' (Householder, reflectors kept) and runs
-    // one-sided Jacobi on B = R2'^T with V; the first wave forms
-    // Z = Q2 V[:, ord] and C1 = R2^{-1} Z_k.
+    // The truncation: the work-group forms M = R1 R2^{-1} (eight lanes per
+    // row for n <= 32, four for n <= 64), M^T = Q2 R2' (Householder,
+    // reflectors kept), one-sided Jacobi on B = R2'^T with V, then
+    // Z = Q2 V[:, ord] and C1 = R2^{-1} Z_k (eight or four lanes per column).
     __shared__ int s_kk;
-    if (n <= 32) {
-      // M row by row with eight lanes per row i (tid / 8), lane s holding
-      // the entries l = s + 8 r: entry j is the row's dot product so far with
-      // column j of R2 (reduced over the eight lanes by DPP), subtracted
-      // from R1's entry and divided by the diagonal
-      const int i = tid >> 3, s = tid & 7;
-      double g[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int j = 0; j < n; ++j) {
-        const double* col = R2 + j * (j + 1) / 2;   // column j of R2 (rows <= j)
-        double p = 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int l = s + 8 * r;
-          const double c = col[l < j ? l : 0];
-          p = fma(l < j ? g[r] : 0.0, c, p);
-        }
-        p = group_sum<8>(p);
-        const double a = (i < n && i <= j) ? R1[upk(i, j)] : 0.0;
-        const double d = col[j];
-        const double gj = (d != 0.0) ? (a - p) / d : 0.0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (j == s + 8 * r) g[r] = gj;
-      }
-      if (i < n) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (s + 8 * r < n) A[i + (s + 8 * r) * SM] = g[r];
-      }
-    } else if (tid < 64) {
-      const int lane = tid;
-      // M column by column (col-major in A); a lane reads only its own row
-      // (four partial sums per entry)
-      for (int j = 0; j < n; ++j) {
-        if (lane < n) {
-          const double* col = R2 + j * (j + 1) / 2;   // column j of R2 (rows <= j)
-          double a0 = (lane <= j) ? R1[upk(lane, j)] : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-          int l = 0;
-          for (; l + 3 < j; l += 4) {
-            a0 = fma(-A[lane + l * SM], col[l], a0);
-            a1 = fma(-A[lane + (l + 1) * SM], col[l + 1], a1);
-            a2 = fma(-A[lane + (l + 2) * SM], col[l + 2], a2);
-            a3 = fma(-A[lane + (l + 3) * SM], col[l + 3], a3);
-          }
-          for (; l < j; ++l) a0 = fma(-A[lane + l * SM], col[l], a0);
-          const double d = col[j];
-          A[lane + j * SM] = (d != 0.0) ? ((a0 + a1) + (a2 + a3)) / d : 0.0;
-        }
-      }
-    }
+    if (n <= 32)
+      sketch_f_m_wg<8, 4>(R1, R2, n, A);
+    else
+      sketch_f_m_wg<4, 16>(R1, R2, n, A);
     // M^T = Q2 R2' by the work-group (reflectors kept), then the reflector
     // tails to R1's packed storage (free now) and B = R2'^T into A
     __syncthreads();
@@ -1691,39 +1680,13 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
         kk = J.cap;
       }
       if (lane == 0) sketch_report(J, dyn, kk, status);
-      if (n > 32) {
-        // Z = Q2 V[:, ord[c]] (lane c, row i at A[i * TLD + c]); A is free now
-        const int c = lane;
-        if (c < kk)
-          for (int i = 0; i < n; ++i) A[i * TLD + c] = V[i + ord[c] * SM];
-        for (int j = n - 1; j >= 0; --j) {
-          const double bj = beta[j];
-          if (c < kk && bj != 0.0) {
-            const double* vj = R1 + j * n - j * (j + 1) / 2;
-            const double v0 = beta[SM + j];
-            double d = v0 * A[j * TLD + c];
-            for (int i = j + 1; i < n; ++i) d = fma(vj[i - j - 1], A[i * TLD + c], d);
-            d *= bj;
-            A[j * TLD + c] -= d * v0;
-            for (int i = j + 1; i < n; ++i) A[i * TLD + c] -= d * vj[i - j - 1];
-          }
-        }
-        // C1 = R2^{-1} Z_k by back substitution in place
-        if (c < kk) {
-          for (int i = n - 1; i >= 0; --i) {
-            double acc = A[i * TLD + c];
-            for (int l = i + 1; l < n; ++l) acc = fma(-R2[upk(i, l)], A[l * TLD + c], acc);
-            const double d = R2[upk(i, i)];
-            const double x = (d != 0.0) ? acc / d : 0.0;
-            A[i * TLD + c] = x;
-            C1[i + (size_t)c * rmax] = x;
-          }
-        }
-      }
       if (lane == 0) s_kk = kk;
     }
     __syncthreads();
-    if (n <= 32) sketch_f_out_wg(V, R1, R2, beta, ord, n, s_kk, C1, rmax);
+    if (n <= 32)
+      sketch_f_out_wg<8, 4>(V, R1, R2, beta, ord, n, s_kk, C1, rmax);
+    else
+      sketch_f_out_wg<4, 16>(V, R1, R2, beta, ord, n, s_kk, C1, rmax);
     if (tid == 0) dyn[J.out_rank_slot] = s_kk;
     return;
   }
