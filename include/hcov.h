@@ -113,7 +113,18 @@ typedef struct {
                              most k singular values above eps sigma_1 (the
                              fixed-rank H-matrices of Sec. 3, Tables 2 and 3);
                              k <= max_rank, and reaching it is no error */
+  int adm_rule;           /* block admissibility [Appendix A]: HCOV_ADM_MIN
+                             (default) the standard Adm_eta of Eq.
+                             (stand_cond), min(diam) <= eta dist;
+                             HCOV_ADM_MAX its max(diam) form; HCOV_ADM_WEAK
+                             the weak admissibility Adm_W of Eq. (wead_adm):
+                             every off-diagonal block of two different
+                             clusters is low rank (eta unused) */
 } hcov_opts;
+
+#define HCOV_ADM_MIN 0
+#define HCOV_ADM_MAX 1
+#define HCOV_ADM_WEAK 2
 
 #define HCOV_QUAD_DIRECT 0
 #define HCOV_QUAD_PCG 1

@@ -117,8 +117,12 @@ def cluster_tree(locs, leaf):
     return t
 
 
-def admissible(bt, bs, eta2):
-    """Squared-form standard admissibility (Appendix A, Eq. (stand_cond))."""
+def admissible(bt, bs, eta2, rule="min"):
+    """Squared-form admissibility of Appendix A: "min" the standard Adm_eta of
+    Eq. (stand_cond), min(diam) <= eta dist; "max" its max(diam) form;
+    "weak" Adm_W of Eq. (wead_adm), true for any two different clusters."""
+    if rule == "weak":
+        return True
     dx = max(max(0.0, bs[0] - bt[1]), bt[0] - bs[1])
     dy = max(max(0.0, bs[2] - bt[3]), bt[2] - bs[3])
     dist2 = dx * dx + dy * dy
@@ -130,10 +134,10 @@ def admissible(bt, bs, eta2):
     exs = bs[1] - bs[0]
     eys = bs[3] - bs[2]
     ds = exs * exs + eys * eys
-    return min(dt, ds) <= eta2 * dist2
+    return (max(dt, ds) if rule == "max" else min(dt, ds)) <= eta2 * dist2
 
 
-def block_tree(tree, eta):
+def block_tree(tree, eta, rule="min"):
     """Leaves of the block cluster tree, breadth first.
 
     Returns an int64 array of rows (level, row_node, col_node, kind) with kind
@@ -147,7 +151,7 @@ def block_tree(tree, eta):
         bb = tree.bbox[l]
         nxt = []
         for t, s in frontier:
-            if t != s and admissible(bb[t], bb[s], eta2):
+            if t != s and admissible(bb[t], bb[s], eta2, rule):
                 out.append((l, t, s, LR))
             elif l == D:
                 out.append((l, t, s, DENSE))

@@ -506,6 +506,7 @@ void hcov_opts_default(hcov_opts* o) {
   o->pcg_tol = 1e-6;
   o->pcg_max_iter = 150;
   o->fixed_rank = 0;
+  o->adm_rule = HCOV_ADM_MIN;
 }
 
 const char* hcov_strerror(int code) {
@@ -532,6 +533,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   if (o.quad_mode != HCOV_QUAD_DIRECT && o.quad_mode != HCOV_QUAD_PCG) return HCOV_EINVAL;
   if (!(o.pcg_tol > 0 && o.pcg_tol < 1) || o.pcg_max_iter < 1) return HCOV_EINVAL;
   if (o.fixed_rank < 0 || o.fixed_rank > o.max_rank) return HCOV_EINVAL;
+  if (o.adm_rule != HCOV_ADM_MIN && o.adm_rule != HCOV_ADM_MAX && o.adm_rule != HCOV_ADM_WEAK) return HCOV_EINVAL;
   std::vector<double> h(2 * n);
   for (int64_t i = 0; i < 2 * n; ++i) {
     if (!std::isfinite(locs[i])) return HCOV_EINVAL;
@@ -597,7 +599,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
     return bail(HCOV_EDEVICE);
   }
   TreeOut T;
-  std::string e = build_trees(d_orig, n, leaf, c->D, eta, lo, c->stream, T);
+  std::string e = build_trees(d_orig, n, leaf, c->D, eta, o.adm_rule, lo, c->stream, T);
   if (!e.empty()) {
     (void)hipFreeAsync(d_orig, c->stream);
     c->err = e;

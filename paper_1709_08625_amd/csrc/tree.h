@@ -17,8 +17,9 @@ struct TreeOut {
 };
 
 // d_loc: device double2[n] in original order.  lo: node starts per level
-// (from the sizes alone).  Returns "" on success.
-std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, double eta,
+// (from the sizes alone).  rule: 0 standard (min), 1 max form, 2 weak
+// admissibility.  Returns "" on success.
+std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, double eta, int rule,
                         const std::vector<std::vector<int64_t>>& lo, hipStream_t st, TreeOut& out);
 
 }  // namespace hc

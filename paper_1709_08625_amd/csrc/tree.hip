@@ -150,7 +150,14 @@ __global__ void k_level_keys(const int* __restrict__ perm, int64_t n, const int6
 }
 
 // ---------------------------------------------------------------- block tree
-__device__ __forceinline__ bool admissible(const double* bt, const double* bs, double eta2) {
+// Admissibility of two clusters of one level by their bounding boxes
+// (Appendix A): rule 0 the standard Adm_eta, min(diam) <= eta dist
+// (Eq. (stand_cond)); rule 1 its max form, max(diam) <= eta dist; rule 2 the
+// weak admissibility Adm_W (Eq. (wead_adm)): any two different clusters.
+// Squared forms, single IEEE operations (no contraction), so that the host
+// reference gets the same bits.
+__device__ __forceinline__ bool admissible(const double* bt, const double* bs, double eta2, int rule) {
+  if (rule == 2) return true;
   double dx = fmax(fmax(0.0, bs[0] - bt[1]), bt[0] - bs[1]);
   double dy = fmax(fmax(0.0, bs[2] - bt[3]), bt[2] - bs[3]);
   double dist2 = __dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy));
@@ -159,18 +166,18 @@ __device__ __forceinline__ bool admissible(const double* bt, const double* bs, d
   double dt = __dadd_rn(__dmul_rn(ext, ext), __dmul_rn(eyt, eyt));
   double exs = bs[1] - bs[0], eys = bs[3] - bs[2];
   double ds = __dadd_rn(__dmul_rn(exs, exs), __dmul_rn(eys, eys));
-  return fmin(dt, ds) <= __dmul_rn(eta2, dist2);
+  return (rule == 1 ? fmax(dt, ds) : fmin(dt, ds)) <= __dmul_rn(eta2, dist2);
 }
 
 // classify: out_kind: 0 dense leaf, 1 LR leaf, 2 subdivided; nch: children count
 __global__ void k_classify(const int2* __restrict__ fr, int cnt, const double* __restrict__ bbl,
-                           double eta2, int is_leaf_level, int* __restrict__ isleaf, int* __restrict__ nch,
+                           double eta2, int rule, int is_leaf_level, int* __restrict__ isleaf, int* __restrict__ nch,
                            int* __restrict__ kind) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt) return;
   int t = fr[i].x, s = fr[i].y;
   int k;
-  if (t != s && admissible(bbl + 4 * t, bbl + 4 * s, eta2))
+  if (t != s && admissible(bbl + 4 * t, bbl + 4 * s, eta2, rule))
     k = 1;
   else if (is_leaf_level)
     k = 0;
@@ -206,7 +213,7 @@ __global__ void k_expand(const int2* __restrict__ fr, int cnt, const int* __rest
 
 static int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
-std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, double eta,
+std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, double eta, int rule,
                         const std::vector<std::vector<int64_t>>& lo, hipStream_t st, TreeOut& out) {
   (void)leaf_max;
   const double2* loc = (const double2*)d_loc;
@@ -332,7 +339,7 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
     std::string g = ensure_work(cnt + 1);
     if (!g.empty()) return g;
     k_classify<<<nblk(cnt, 256), 256, 0, st>>>(fr, (int)cnt, bbox_all + ((int64_t(1) << l) - 1) * 4,
-                                                eta2, l == D, isl, nch, knd);
+                                                eta2, rule, l == D, isl, nch, knd);
     TCHK(hipGetLastError());
     size_t need2 = 0;
     TCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, need2, isl, lpos, (int)cnt + 1, st));

@@ -17,6 +17,7 @@ HOST, DEVICE = 0, 1
 FP64, MIXED = 0, 1
 SAT_RETRY, SAT_ERROR = 0, 1
 QUAD_DIRECT, QUAD_PCG = 0, 1
+ADM_MIN, ADM_MAX, ADM_WEAK = 0, 1, 2
 
 
 class Theta(C.Structure):
@@ -43,7 +44,8 @@ class Opts(C.Structure):
                 ("fuse_solve", C.c_int), ("mem_cap_bytes", C.c_size_t), ("alloc", ALLOC_FN),
                 ("free", FREE_FN), ("alloc_user", C.c_void_p), ("use_graphs", C.c_int),
                 ("oversample", C.c_int), ("on_saturation", C.c_int), ("keep_matrix", C.c_int),
-                ("quad_mode", C.c_int), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int), ("fixed_rank", C.c_int)]
+                ("quad_mode", C.c_int), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int), ("fixed_rank", C.c_int),
+                ("adm_rule", C.c_int)]
 
 
 class Stats(C.Structure):

@@ -282,3 +282,29 @@ def test_state_errors():
         h.set_theta((1.0, -0.1, 0.5, 1e-4))
     assert e.value.code == hcov.EINVAL
     h.close()
+
+
+# ------------------------------------------------------------------ admissibility variants
+@pytest.mark.parametrize("rule,n,eps", [("max", 2000, 1e-8), ("weak", 1200, 1e-7)])
+def test_admissibility_variants_trees_and_loglik(rule, n, eps):
+    # Appendix A: the max(diam) form of Adm_eta and the weak admissibility
+    # Adm_W (Eq. (wead_adm)); the block trees match the reference bit for bit
+    # and the likelihood the dense oracle at the FP64 tolerance
+    hcov = _hc()
+    code = {"max": hcov.ADM_MAX, "weak": hcov.ADM_WEAK}[rule]
+    th = (1.0, 0.3, 1.5, 1e-4)
+    locs, xi = workloads.uniform(n, seed=41)
+    t = trees.cluster_tree(locs, 32)
+    ref = trees.block_tree(t, 2.0, rule)
+    h = hcov.HCov(locs, th, eps=eps, leaf=32, eta=2.0, opts={"adm_rule": code})
+    D, bbox, blocks = h.tree()
+    assert np.array_equal(blocks, ref)
+    z = dense.sample_field(locs, xi, *th)
+    ll0, ld0, q0 = dense.loglik_parts(locs, z, *th)
+    ll, ld, q = h.loglik(z)
+    S = scale(n, ld0, q0)
+    st = h.stats()
+    print(f"{rule}: blocks {len(blocks)} (lr {st['n_lr_blocks']}), max rank {st['max_rank_seen']}, "
+          f"|dL|/S {abs(ll - ll0) / S:.2e}")
+    assert abs(ll - ll0) / S < 1e-6
+    h.close()

@@ -162,3 +162,61 @@ def test_duplicate_points_do_not_break_the_tree():
     assert np.array_equal(np.sort(t.perm), np.arange(100))
     leaves = trees.block_tree(t, 2.0)
     assert len(leaves) > 0
+
+
+# ---------------------------------------------------------------- admissibility variants
+@pytest.mark.parametrize("rule", ["min", "max", "weak"])
+def test_variant_block_trees_tile_lower_triangle(rule):
+    n, leaf = 900, 16
+    locs, _ = workloads.uniform(n, seed=5)
+    t = trees.cluster_tree(locs, leaf)
+    leaves = trees.block_tree(t, 2.0, rule)
+    cover = np.zeros((n, n), dtype=np.int32)
+    for l, a, b, kind in leaves:
+        ra, rb = t.ranges[l][a], t.ranges[l][b]
+        cover[ra[0]:ra[1], rb[0]:rb[1]] += 1
+        if kind == trees.DENSE:
+            assert l == t.depth and a == b or rule != "weak"
+    low = np.tril(np.ones((n, n), dtype=bool))
+    assert np.all(cover[low] == 1)
+
+
+def test_weak_admissibility_is_the_sibling_pattern():
+    # Eq. (wead_adm): a block of two different clusters of one level is
+    # admissible, so the lower triangle splits into the off-diagonal sibling
+    # blocks (2i+1, 2i) of every level and the dense diagonal leaves
+    locs, _ = workloads.uniform(777, seed=6)
+    t = trees.cluster_tree(locs, 16)
+    D = t.depth
+    want = []
+    frontier = [0]
+    for l in range(D + 1):
+        if l == D:
+            want += [(l, i, i, trees.DENSE) for i in frontier]
+            break
+        want += [(l + 1, 2 * i + 1, 2 * i, trees.LR) for i in frontier]
+        frontier = [c for i in frontier for c in (2 * i, 2 * i + 1)]
+    got = trees.block_tree(t, 2.0, "weak")
+    assert sorted(map(tuple, got.tolist())) == sorted(want)
+
+
+def test_max_admissibility_on_point_sets_and_refines_min():
+    # the max(diam) form is the stricter condition: every low-rank leaf
+    # satisfies max(diam A, diam B) <= eta dist(A, B) on its point sets, and
+    # every such block is also admissible in the standard (min) sense
+    locs, _ = workloads.uniform(1200, seed=22)
+    t = trees.cluster_tree(locs, 24)
+    mx = trees.block_tree(t, 2.0, "max")
+    mn = trees.block_tree(t, 2.0, "min")
+    lr = mx[mx[:, 3] == trees.LR]
+    assert len(lr) > 0
+    for l, a, b, _ in lr:
+        A = locs[t.perm[slice(*t.ranges[l][a])]]
+        B = locs[t.perm[slice(*t.ranges[l][b])]]
+        dA = np.sqrt(((A[:, None] - A[None]) ** 2).sum(-1)).max()
+        dB = np.sqrt(((B[:, None] - B[None]) ** 2).sum(-1)).max()
+        dist = np.sqrt(((A[:, None] - B[None]) ** 2).sum(-1)).min()
+        assert dist > 0 and max(dA, dB) <= 2.0 * dist
+        assert trees.admissible(t.bbox[l][a], t.bbox[l][b], 4.0, "min")
+    # the stricter rule never has fewer blocks
+    assert len(mx) >= len(mn)
