@@ -180,6 +180,37 @@ def fit128k(args, hcov, workloads):
     }
 
 
+def paramid_bench(args, hcov, workloads):
+    """Parameter identification (Sec. 5.1, Fig. 9): Z0 = L~ xi at n0 uniform
+    locations from theta* = (sigma2 1, ell 0.0864, nu 0.5), nugget 1e-4
+    (eps 1e-7, leaf 128); replicate subsets of n points, each fitted by
+    Nelder-Mead from theta* x (1.2, 0.8, 1.1) (eps 1e-7, leaf 64)."""
+    from paper_1709_08625_amd import paramid
+    sizes = [int(x) for x in args.sizes.split(",")]
+    t0 = time.perf_counter()
+    locs0, xi0 = workloads.uniform(args.n0, seed=0)
+    z0 = paramid.draw_field(locs0, xi0)
+    t_draw = time.perf_counter() - t0
+    progress(f"Z0 drawn at n0={args.n0} in {t_draw:.1f} s")
+    start = tuple(np.array(paramid.TRUTH) * np.array([1.2, 0.8, 1.1]))
+    t1 = time.perf_counter()
+    fits = paramid.identify(locs0, z0, sizes, args.replicates, start, max_evals=args.evals, progress=progress)
+    t_fit = time.perf_counter() - t1
+    evals = sum(f["evals"] for f in fits)
+    return {
+        "metric": "parameter identification: likelihood evaluations/sec over replicate Nelder-Mead fits",
+        "value": evals / t_fit, "unit": "evals/s", "n_gpus": 1, "steps": len(fits), "warmup": 0,
+        "ms_per_step": 1e3 * t_fit / max(len(fits), 1), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"Z0 = L~xi at n0={args.n0} uniform locations, theta* = (sigma2 1, ell 0.0864, "
+                               f"nu 0.5), nugget 1e-4; {args.replicates} replicates per n in {sizes}, "
+                               f"{args.evals} evaluations per fit"},
+        "truth": {"sigma2": paramid.TRUTH[0], "ell": paramid.TRUTH[1], "nu": paramid.TRUTH[2]},
+        "draw_s": t_draw, "fit_s": t_fit, "evaluations": evals,
+        "summary": paramid.summarise(fits), "fits": fits,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -190,7 +221,10 @@ def main():
     ap.add_argument("--profile-kind", default="gemm")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch the sweep stage by stage instead of replaying captured graph segments")
-    ap.add_argument("--workload", default="loglik512k", choices=["loglik512k", "serving", "fit128k"])
+    ap.add_argument("--workload", default="loglik512k", choices=["loglik512k", "serving", "fit128k", "paramid"])
+    ap.add_argument("--n0", type=int, default=2000000, help="paramid: size of the field Z0")
+    ap.add_argument("--sizes", default="2000,4000,8000,16000", help="paramid: subset sizes")
+    ap.add_argument("--replicates", type=int, default=5, help="paramid: fits per subset size")
     ap.add_argument("--evals", type=int, default=30)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--requests", type=int, default=96)
@@ -212,6 +246,9 @@ def main():
         return
     if args.workload == "fit128k":
         print(json.dumps(fit128k(args, hcov, workloads)))
+        return
+    if args.workload == "paramid":
+        print(json.dumps(paramid_bench(args, hcov, workloads)))
         return
     n = args.n
     theta0 = (1.0, 0.08, 0.8, 1e-4)
