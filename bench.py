@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X FP64 vector (= FP64 matrix) peak
+PEAK_HBM_TBS = 8.0           # MI355X HBM3E bandwidth
 
 
 def progress(msg):
@@ -298,12 +299,19 @@ def main():
     H.profile_begin(args.profile_kind)
     step(thetas[-1])
     torch.cuda.synchronize()
-    launches, kern_ms, kern_flops = H.profile_end()
+    launches, kern_ms, kern_flops, kern_bytes = H.profile_end()
     progress("roofline evaluation done")
     H.close()
 
     avg_us = 1e3 * kern_ms / max(launches, 1)
-    achieved = (kern_flops / max(launches, 1)) / (avg_us * 1e-6) / 1e12 if launches else 0.0
+    fl_launch = kern_flops / max(launches, 1)
+    by_launch = kern_bytes / max(launches, 1)
+    tflops = fl_launch / (avg_us * 1e-6) / 1e12 if launches else 0.0
+    gbs = by_launch / (avg_us * 1e-6) / 1e9 if launches else 0.0
+    # the bound that applies: a launch whose algorithmic intensity is below
+    # the FP64 ridge (78.6 TFLOP/s / 8 TB/s = 9.8 flop/B) is HBM bound
+    intensity = fl_launch / by_launch if by_launch > 0 else float("inf")
+    hbm_bound = intensity < PEAK_FP64_TFLOPS / PEAK_HBM_TBS
     rec = {
         "metric": "loglik evals/sec at n=512k (H-Cholesky+logdet+solve); p50/p99 latency",
         "value": args.steps / total,
@@ -334,12 +342,18 @@ def main():
                       "sketch_retries": st["n_sketch_retries"],
                       "mean_sketch_width": st["mean_sketch_width"]},
         # FP64 tiles of k_gemm run on the matrix cores (dense FP64 MFMA peak);
-        # in mixed precision part of the work is FP32 but the FP64 peak is kept
-        "roofline": {"bound": "mfma" if args.profile_kind == "gemm" else "alu", "kernel": f"k_{args.profile_kind}",
-                     "achieved": achieved,
-                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+        # its products are thin (k = ranks 10-40), so their algorithmic
+        # intensity sits below the ridge and HBM bandwidth is the bound
+        "roofline": {"bound": "hbm" if hbm_bound else "mfma", "kernel": f"k_{args.profile_kind}",
+                     "achieved": gbs if hbm_bound else tflops,
+                     "peak": 1e3 * PEAK_HBM_TBS if hbm_bound else PEAK_FP64_TFLOPS,
+                     "unit": "GB/s" if hbm_bound else "TFLOP/s",
+                     "frac": gbs / (1e3 * PEAK_HBM_TBS) if hbm_bound else tflops / PEAK_FP64_TFLOPS,
                      "traffic": None, "launches": launches, "avg_launch_us": avg_us,
-                     "algorithmic_flops_per_launch": kern_flops / max(launches, 1)},
+                     "algorithmic_flops_per_launch": fl_launch, "algorithmic_bytes_per_launch": by_launch,
+                     "intensity_flop_per_byte": intensity, "achieved_tflops": tflops,
+                     "frac_of_fp64_mfma": tflops / PEAK_FP64_TFLOPS, "achieved_gbs": gbs,
+                     "frac_of_hbm": gbs / (1e3 * PEAK_HBM_TBS)},
         "loglik_last": lls[-1],
     }
     if not args.no_cpu:

@@ -329,12 +329,16 @@ int hcov_fit(hcov_ctx* ctx, const double* z, int where, const double* theta0, co
  * 1 TSQR segment, 2 TSQR reduce, 3 small SVD / pivoted QR, 4 diagonal leaf
  * potrf, 5 triangular solve, 9 multiplication by a stored leaf inverse) is
  * bracketed by HIP events on the stream it runs on.  hcov_profile_end
- * synchronises and returns the launch count, the summed event time (ms) and
+ * synchronises and returns the launch count, the summed event time (ms),
  * the algorithmic FP64 flops of those launches (GEMM: 2 m n k per product;
  * potrf: p^3/3; solve and multiplication: p^2 per column; 0 for the other
- * kinds).  Other values of kind are EINVAL. */
+ * kinds) and their algorithmic bytes (every operand read once, every output
+ * written once and read once more when accumulated: GEMM 8 (m k + k n) per
+ * product plus 8 m n or 16 m n per job, 4-byte elements in FP32 jobs;
+ * potrf 16 p^2; solve and multiplication 8 p (p + 2 columns)).  Any output
+ * pointer may be NULL.  Other values of kind are EINVAL. */
 int hcov_profile_begin(hcov_ctx* ctx, int stage_kind);
-int hcov_profile_end(hcov_ctx* ctx, int64_t* launches, double* total_ms, double* flops);
+int hcov_profile_end(hcov_ctx* ctx, int64_t* launches, double* total_ms, double* flops, double* bytes);
 
 /* Eq. (3) on the device for n given distances h (host arrays): test access to
  * the device Matérn / K_nu evaluation used by the assembly. */

@@ -73,7 +73,7 @@ struct hcov_ctx {
   // replayed on gstream between two events of the caller's stream
   hipStream_t gstream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  std::vector<hipGraphExec_t> gexec[2];   // segments of whole steps, replayed in order
+  std::vector<hipGraphExec_t> gexec;      // segments of whole steps, replayed in order
   bool graph_failed = false;
   int64_t n_replays = 0;
   int64_t n_retries = 0;       // factorisations redone with wider sketches
@@ -228,9 +228,12 @@ inline int dyn_value(const std::vector<int>& dyn, const Dim& d) {
   return v < d.maxv ? v : d.maxv;
 }
 
-// algorithmic FP64 flops of one stage with the current dynamic dimensions
-double stage_flops(const Plan& P, const std::vector<int>& dyn, const Stage& s) {
-  double f = 0.0;
+// Algorithmic work of one stage with the current dynamic dimensions: FP64
+// flops and the bytes its operands must move at least once (each product
+// reads its A and B operands; each job writes its output and, when it
+// accumulates, reads it too; elements of 8 bytes, 4 for FP32 jobs).
+void stage_work(const Plan& P, const std::vector<int>& dyn, const Stage& s, double* flops, double* bytes) {
+  double f = 0.0, b = 0.0;
   if (s.kind == ST_GEMM) {
     // the tiles of a launch are sorted by cost, so one job's tiles need not
     // be adjacent: count every job of the launch once
@@ -242,24 +245,43 @@ double stage_flops(const Plan& P, const std::vector<int>& dyn, const Stage& s) {
     for (int j : jobs) {
       const GemmJob& J = P.gjobs[j];
       int m = dyn_value(dyn, J.m), n = dyn_value(dyn, J.n);
+      if (m <= 0 || n <= 0) continue;
+      const double el = J.fp32 ? 4.0 : 8.0;
+      b += 8.0 * double(m) * double(n) * (J.zero ? 1.0 : 2.0);
       for (int q = J.p0; q < J.p1; ++q) {
         const GemmProd& G = P.gprods[q];
         int k = dyn_value(dyn, G.k);
         int mi = std::min(dyn_value(dyn, G.mi), m - G.i0), nj = std::min(dyn_value(dyn, G.nj), n - G.j0);
-        if (mi > 0 && nj > 0 && k > 0) f += (G.tb == 2 ? 1.0 : 2.0 * k) * double(mi) * double(nj);
+        if (mi > 0 && nj > 0 && k > 0) {
+          if (G.tb == 2) {   // partial-sum addition: one operand of mi x nj
+            f += double(mi) * double(nj);
+            b += el * double(mi) * double(nj);
+          } else {
+            f += 2.0 * k * double(mi) * double(nj);
+            b += el * double(k) * (double(mi) + double(nj));
+          }
+        }
       }
     }
   } else if (s.kind == ST_LEAF) {
-    for (int t = s.begin; t < s.end; ++t) f += double(P.leafs[t].p) * P.leafs[t].p * P.leafs[t].p / 3.0;
+    for (int t = s.begin; t < s.end; ++t) {
+      const double p = P.leafs[t].p;
+      f += p * p * p / 3.0;
+      b += 16.0 * p * p;
+    }
   } else if (s.kind == ST_TRSM || s.kind == ST_TRMM) {
     for (int t = s.begin; t < s.end; ++t) {
       const TrsmJob& J = P.trsms[t];
       int nc = dyn_value(dyn, J.ncols);
       int cw = std::min(J.cw, nc - J.c0);
-      if (cw > 0) f += double(J.p) * J.p * cw;
+      if (cw > 0) {
+        f += double(J.p) * J.p * cw;
+        b += 8.0 * double(J.p) * (J.p + 2.0 * cw);
+      }
     }
   }
-  return f;
+  *flops = f;
+  *bytes = b;
 }
 
 // Internal (positive) result of a factorisation whose sketches saturated
@@ -367,7 +389,7 @@ int reduce_dev(hcov_ctx* c, const double* x, int64_t n, int mode, double* out, c
 // failure leaves the context on per-stage launches.
 constexpr size_t GRAPH_STAGES = 1500;
 
-void capture_sweep(hcov_ctx* c, const std::vector<std::vector<Stage>>& steps, int gi) {
+void capture_sweep(hcov_ctx* c, const std::vector<std::vector<Stage>>& steps) {
   hipStream_t user = c->stream;
   c->stream = c->gstream;
   bool ok = true;
@@ -389,13 +411,13 @@ void capture_sweep(hcov_ctx* c, const std::vector<std::vector<Stage>>& steps, in
     hipGraphExec_t ge = nullptr;
     ok = ok && ended && g && hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) == hipSuccess;
     if (g) (void)hipGraphDestroy(g);
-    if (ok) c->gexec[gi].push_back(ge);
+    if (ok) c->gexec.push_back(ge);
   }
   c->stream = user;
   if (!ok) {
-    for (auto ge : c->gexec[gi])
+    for (auto ge : c->gexec)
       if (ge) (void)hipGraphExecDestroy(ge);
-    c->gexec[gi].clear();
+    c->gexec.clear();
     c->graph_failed = true;
     c->err.clear();
     (void)hipGetLastError();
@@ -408,13 +430,14 @@ int factor(hcov_ctx* c, const double* z_dev_cluster, bool fuse) {
   int r = reset_status(c);
   if (r) return r;
   (void)z_dev_cluster;   // with fuse, the right-hand side is already in B_RHS
-  const auto& steps = fuse ? c->plan.steps : c->plan.steps_nofuse;
-  const int gi = fuse ? 1 : 0;
-  if (c->gstream && c->prof_kind < 0 && !c->graph_failed && c->gexec[gi].empty()) capture_sweep(c, steps, gi);
-  if (c->gstream && c->prof_kind < 0 && !c->gexec[gi].empty()) {
+  // without an observation vector the sweep's right-hand-side column is zero
+  if (!fuse) HIPCHK(c, launch_fill_value(c->d_buf[B_RHS], c->n, 0.0, c->stream));
+  const auto& steps = c->plan.steps;
+  if (c->gstream && c->prof_kind < 0 && !c->graph_failed && c->gexec.empty()) capture_sweep(c, steps);
+  if (c->gstream && c->prof_kind < 0 && !c->gexec.empty()) {
     HIPCHK(c, hipEventRecord(c->ev_in, c->stream));
     HIPCHK(c, hipStreamWaitEvent(c->gstream, c->ev_in, 0));
-    for (auto ge : c->gexec[gi]) HIPCHK(c, hipGraphLaunch(ge, c->gstream));
+    for (auto ge : c->gexec) HIPCHK(c, hipGraphLaunch(ge, c->gstream));
     c->n_replays += 1;
     HIPCHK(c, hipEventRecord(c->ev_out, c->gstream));
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_out, 0));
@@ -1220,9 +1243,8 @@ void hcov_destroy(hcov_ctx* c) {
   if (c->gstream) (void)hipStreamSynchronize(c->gstream);
   if (c->stream) hipStreamSynchronize(c->stream);
   else hipDeviceSynchronize();
-  for (auto& v : c->gexec)
-    for (auto g : v)
-      if (g) (void)hipGraphExecDestroy(g);
+  for (auto g : c->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
   if (c->stream2) (void)hipStreamDestroy(c->stream2);
   if (c->gstream) (void)hipStreamDestroy(c->gstream);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
@@ -1248,24 +1270,28 @@ int hcov_profile_begin(hcov_ctx* c, int stage_kind) {
   return HCOV_OK;
 }
 
-int hcov_profile_end(hcov_ctx* c, int64_t* launches, double* total_ms, double* flops) {
+int hcov_profile_end(hcov_ctx* c, int64_t* launches, double* total_ms, double* flops, double* bytes) {
   if (!c) return HCOV_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   std::vector<int> dyn(c->plan.n_dyn + 1);
   HIPCHK(c, hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  double ms = 0.0, fl = 0.0;
+  double ms = 0.0, fl = 0.0, by = 0.0;
   for (size_t i = 0; i < c->prof_ev.size(); ++i) {
     float t = 0.f;
     HIPCHK(c, hipEventElapsedTime(&t, c->prof_ev[i].first, c->prof_ev[i].second));
     ms += t;
-    fl += stage_flops(c->plan, dyn, c->prof_stages[i]);
+    double f1 = 0.0, b1 = 0.0;
+    stage_work(c->plan, dyn, c->prof_stages[i], &f1, &b1);
+    fl += f1;
+    by += b1;
     (void)hipEventDestroy(c->prof_ev[i].first);
     (void)hipEventDestroy(c->prof_ev[i].second);
   }
   if (launches) *launches = int64_t(c->prof_ev.size());
   if (total_ms) *total_ms = ms;
   if (flops) *flops = fl;
+  if (bytes) *bytes = by;
   c->prof_kind = -1;
   c->prof_ev.clear();
   c->prof_stages.clear();

@@ -173,15 +173,24 @@ class Builder {
     int32_t nj = int32_t(P.gjobs.size()) - job_base;
     if (nj <= 0) return;
     int32_t t0 = int32_t(P.gtiles.size());
+    // estimated k chunks per tile, accumulated over the tiles each product spans
+    std::vector<int> tcost;
     for (int32_t j = 0; j < nj; ++j) {
       GemmJob& g = P.gjobs[job_base + j];
       g.p0 = int32_t(P.gprods.size());
+      const int mt = (g.m.maxv + TM - 1) / TM, nt = (g.n.maxv + TN - 1) / TN;
+      const size_t tb = tcost.size();
+      tcost.resize(tb + size_t(mt) * nt, 0);
       for (auto& p : pending_prods[j]) {
         P.gprods.push_back(p);
         if (p.A.buf == B_RHS || p.B.buf == B_RHS) g.fp32 = 0;   // the solve stays FP64
+        const int c = p.tb == 2 ? 1 : chunks(est_k(p.k));
+        const int a0 = std::max(0, p.i0 / TM), a1 = std::min(mt, (p.i0 + p.mi.maxv + TM - 1) / TM);
+        const int b0 = std::max(0, p.j0 / TN), b1 = std::min(nt, (p.j0 + p.nj.maxv + TN - 1) / TN);
+        for (int a = a0; a < a1; ++a)
+          for (int b = b0; b < b1; ++b) tcost[tb + size_t(a) * nt + b] += c;
       }
       g.p1 = int32_t(P.gprods.size());
-      int mt = (g.m.maxv + TM - 1) / TM, nt = (g.n.maxv + TN - 1) / TN;
       for (int a = 0; a < mt; ++a)
         for (int b = 0; b < nt; ++b) P.gtiles.push_back(GemmTile{job_base + j, a, b, 0});
     }
@@ -193,18 +202,7 @@ class Builder {
       // with more tiles than resident work-groups is scheduled longest first
       std::vector<std::pair<int, int32_t>> cost;
       cost.reserve(size_t(t1 - t0));
-      for (int32_t t = t0; t < t1; ++t) {
-        const GemmTile& T = P.gtiles[t];
-        const GemmJob& g = P.gjobs[T.job];
-        int c = 0;
-        for (int32_t q = g.p0; q < g.p1; ++q) {
-          const GemmProd& pr = P.gprods[q];
-          const int i1 = pr.i0 + pr.mi.maxv, j1 = pr.j0 + pr.nj.maxv;
-          if (i1 <= T.ti * TM || pr.i0 >= (T.ti + 1) * TM || j1 <= T.tj * TN || pr.j0 >= (T.tj + 1) * TN) continue;
-          c += pr.tb == 2 ? 1 : chunks(est_k(pr.k));
-        }
-        cost.emplace_back(-c, t);
-      }
+      for (int32_t t = t0; t < t1; ++t) cost.emplace_back(-tcost[size_t(t - t0)], t);
       std::stable_sort(cost.begin(), cost.end(),
                        [](const std::pair<int, int32_t>& x, const std::pair<int, int32_t>& y) { return x.first < y.first; });
       std::vector<GemmTile> sorted;
@@ -1314,8 +1312,9 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
   P.n_dyn = dyn;
   Bd.build_recompress();
   Bd.core_base = P.pers_elems;   // cores live above the assembly R slots
+  // one sweep serves both uses: without an observation vector the fused
+  // right-hand side is a zero column (a few flops per step)
   Bd.build_steps(true, P.steps);
-  Bd.build_steps(false, P.steps_nofuse);
   Bd.build_solves();
   Bd.build_matvec();
   if (Bd.dyn_max > P.n_dyn) P.n_dyn = Bd.dyn_max;

@@ -187,8 +187,7 @@ struct Plan {
 
   // schedules
   std::vector<Stage> recomp_stages;              // assembly recompression
-  std::vector<std::vector<Stage>> steps;          // factorisation sweep (with fused RHS)
-  std::vector<std::vector<Stage>> steps_nofuse;   // sweep without the RHS
+  std::vector<std::vector<Stage>> steps;          // factorisation sweep (with the fused RHS column)
   int64_t scr_elems = 0;                          // per-step scratch size
   int64_t pers_elems = 0;                         // persistent scratch size
   int64_t omega_rows = 0;

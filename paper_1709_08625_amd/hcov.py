@@ -112,7 +112,7 @@ def lib():
         L.hcov_server_destroy.argtypes = [C.c_void_p]
         L.hcov_server_destroy.restype = None
         L.hcov_profile_begin.argtypes = [C.c_void_p, C.c_int]
-        L.hcov_profile_end.argtypes = [C.c_void_p, C.POINTER(C.c_int64), dp, dp]
+        L.hcov_profile_end.argtypes = [C.c_void_p, C.POINTER(C.c_int64), dp, dp, dp]
         _lib = L
     return _lib
 
@@ -370,11 +370,13 @@ class HCov:
         self._chk(lib().hcov_profile_begin(self._ctx, STAGE_KINDS[kind] if isinstance(kind, str) else int(kind)))
 
     def profile_end(self):
+        """(launches, summed kernel ms, algorithmic flops, algorithmic bytes)."""
         n = C.c_int64()
         ms = C.c_double()
         fl = C.c_double()
-        self._chk(lib().hcov_profile_end(self._ctx, C.byref(n), C.byref(ms), C.byref(fl)))
-        return n.value, ms.value, fl.value
+        by = C.c_double()
+        self._chk(lib().hcov_profile_end(self._ctx, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)))
+        return n.value, ms.value, fl.value, by.value
 
     def perm(self):
         p = np.empty(self.n, dtype=np.int64)
