@@ -339,6 +339,9 @@ int hcov_fit(hcov_ctx* ctx, const double* z, int where, const double* theta0, co
  * pointer may be NULL.  Other values of kind are EINVAL. */
 int hcov_profile_begin(hcov_ctx* ctx, int stage_kind);
 int hcov_profile_end(hcov_ctx* ctx, int64_t* launches, double* total_ms, double* flops, double* bytes);
+/* The per-launch durations (ms, launch order) of the last profiling session:
+ * up to max_n values into times_ms (may be NULL), the count into *n_out. */
+int hcov_profile_times(const hcov_ctx* ctx, double* times_ms, int64_t max_n, int64_t* n_out);
 
 /* Eq. (3) on the device for n given distances h (host arrays): test access to
  * the device Matérn / K_nu evaluation used by the assembly. */

@@ -80,6 +80,7 @@ struct hcov_ctx {
   int sat_last = 0;            // saturated sketches of the last factorisation
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   std::vector<Stage> prof_stages;
+  std::vector<double> prof_times;   // per-launch ms of the last profiling session
   // state
   bool assembled = false, factored = false;
   double ms_tree = 0, ms_asm = 0, ms_fact = 0, ms_solve = 0;
@@ -1277,10 +1278,12 @@ int hcov_profile_end(hcov_ctx* c, int64_t* launches, double* total_ms, double* f
   HIPCHK(c, hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double ms = 0.0, fl = 0.0, by = 0.0;
+  c->prof_times.clear();
   for (size_t i = 0; i < c->prof_ev.size(); ++i) {
     float t = 0.f;
     HIPCHK(c, hipEventElapsedTime(&t, c->prof_ev[i].first, c->prof_ev[i].second));
     ms += t;
+    c->prof_times.push_back(t);
     double f1 = 0.0, b1 = 0.0;
     stage_work(c->plan, dyn, c->prof_stages[i], &f1, &b1);
     fl += f1;
@@ -1295,6 +1298,15 @@ int hcov_profile_end(hcov_ctx* c, int64_t* launches, double* total_ms, double* f
   c->prof_kind = -1;
   c->prof_ev.clear();
   c->prof_stages.clear();
+  return HCOV_OK;
+}
+
+int hcov_profile_times(const hcov_ctx* c, double* times_ms, int64_t max_n, int64_t* n_out) {
+  if (!c) return HCOV_EINVAL;
+  const int64_t n = int64_t(c->prof_times.size());
+  if (n_out) *n_out = n;
+  if (times_ms)
+    for (int64_t i = 0; i < std::min(n, max_n); ++i) times_ms[i] = c->prof_times[size_t(i)];
   return HCOV_OK;
 }
 

@@ -113,6 +113,7 @@ def lib():
         L.hcov_server_destroy.restype = None
         L.hcov_profile_begin.argtypes = [C.c_void_p, C.c_int]
         L.hcov_profile_end.argtypes = [C.c_void_p, C.POINTER(C.c_int64), dp, dp, dp]
+        L.hcov_profile_times.argtypes = [C.c_void_p, dp, C.c_int64, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -377,6 +378,14 @@ class HCov:
         by = C.c_double()
         self._chk(lib().hcov_profile_end(self._ctx, C.byref(n), C.byref(ms), C.byref(fl), C.byref(by)))
         return n.value, ms.value, fl.value, by.value
+
+    def profile_times(self):
+        """Per-launch durations (ms) of the last profiling session."""
+        n = C.c_int64()
+        self._chk(lib().hcov_profile_times(self._ctx, None, 0, C.byref(n)))
+        t = np.empty(n.value)
+        self._chk(lib().hcov_profile_times(self._ctx, _dp(t), n.value, C.byref(n)))
+        return t
 
     def perm(self):
         p = np.empty(self.n, dtype=np.int64)
