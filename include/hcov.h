@@ -326,7 +326,7 @@ int hcov_fit(hcov_ctx* ctx, const double* z, int where, const double* theta0, co
 
 /* Kernel timing: between hcov_profile_begin(ctx, kind) and
  * hcov_profile_end, every launch of the given stage kind (0 grouped GEMM,
- * 1 TSQR segment, 2 TSQR reduce, 3 small SVD / pivoted QR, 4 diagonal leaf
+ * by either GEMM kernel, 1 TSQR segment, 2 TSQR reduce, 3 small SVD / pivoted QR, 4 diagonal leaf
  * potrf, 5 triangular solve, 9 multiplication by a stored leaf inverse) is
  * bracketed by HIP events on the stream it runs on.  hcov_profile_end
  * synchronises and returns the launch count, the summed event time (ms),

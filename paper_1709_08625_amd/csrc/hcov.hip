@@ -207,7 +207,7 @@ int run_stages(hcov_ctx* c, const std::vector<Stage>& st, const LaunchCtx* Lx = 
       continue;
     }
     hipStream_t sm = s.lane ? c->stream2 : c->stream;
-    if (s.kind == c->prof_kind) {
+    if (s.kind == c->prof_kind || (s.kind == ST_GEMM_WIDE && c->prof_kind == ST_GEMM)) {
       hipEvent_t a, b;
       HIPCHK(c, hipEventCreate(&a));
       HIPCHK(c, hipEventCreate(&b));
@@ -235,7 +235,7 @@ inline int dyn_value(const std::vector<int>& dyn, const Dim& d) {
 // accumulates, reads it too; elements of 8 bytes, 4 for FP32 jobs).
 void stage_work(const Plan& P, const std::vector<int>& dyn, const Stage& s, double* flops, double* bytes) {
   double f = 0.0, b = 0.0;
-  if (s.kind == ST_GEMM) {
+  if (s.kind == ST_GEMM || s.kind == ST_GEMM_WIDE) {
     // the tiles of a launch are sorted by cost, so one job's tiles need not
     // be adjacent: count every job of the launch once
     std::vector<int> jobs;

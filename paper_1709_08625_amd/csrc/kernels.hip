@@ -69,44 +69,53 @@ struct ProdMeta {
 // additions (tb == 2) go to on_add(M); every other live product streams its
 // k range through LDS in chunks of GK, the next (product, chunk) pair's
 // global loads in flight while on_chunk(kl) consumes the current chunk.
-template <class T, class AddF, class ChunkF>
+//
+// With G > 1 groups of 256 threads (a work-group of 256 G threads) the
+// groups share the descriptors and work in lockstep on their own LDS chunk
+// buffers (As, Bs point to the calling group's): group g takes the pairs and
+// the additions whose index in the tile's order is g mod G, so G chunks of
+// one tile are in flight at once.  Each group accumulates its own partial
+// sum; the caller adds them in group order.
+template <class T, int G = 1, class AddF, class ChunkF>
 __device__ __forceinline__ void gemm_products(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
                                               const GemmJob& J, const GemmProd* __restrict__ prods, int m,
                                               int n, int r0, int c0, T (*As)[GT + 1], T (*Bs)[GT + 1],
                                               ProdMeta* pm, AddF on_add, ChunkF on_chunk) {
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x & 255;
+  const int grp = G > 1 ? uniform_int(int(threadIdx.x >> 8)) : 0;
   // element e of a chunk: A chunk is GT x GK, B chunk GK x GT; the index
   // split follows the operand's storage order so that lanes coalesce.  The
-  // loads of the next chunk stay in flight while the current one is used:
-  // they read a valid element of the product even outside its extent (bit r
-  // of ma / mb records which are real), and the mask and scale are applied
-  // only when the chunk goes to LDS.  Descriptor fields are the same in
-  // every lane: scalar registers, so that the operand layout is one uniform
-  // branch and the loads take a scalar base address.
+  // loads of the next chunk stay in flight while the current one is used.
+  // They are buffer loads over a 2 GiB range from the operand's start
+  // (scalar base, 32-bit lane offset): an element outside the product's
+  // extent gets the offset 2^31, outside that range, and the hardware
+  // returns 0 for it without an access, so a chunk arrives masked and goes
+  // to LDS as it is.  Descriptor
+  // fields are the same in every lane: scalar registers, so that the
+  // operand layout is one uniform branch.
   double ra[GR], rb[GR];
-  unsigned ma = 0, mb = 0;
   // element r of a thread: with the operand's leading index contiguous
   // (ta == 0 / tb == 1) the thread keeps index tid % 64 and takes k steps of
   // 4 (k = tid / 64 + 4 r); with k contiguous it keeps k = tid % 32 and takes
   // index steps of 8 (tid / 32 + 8 r).  Either way element r sits at a
-  // fixed per-thread byte offset plus r times a uniform stride (32-bit: the
-  // planner keeps every operand below 2^29 elements), and a range check is
-  // one unsigned compare.
-  auto fetch_op = [&](const HC_GLOBAL char* base, int lead_major, int ld, int lo, int hi, int g0, int kp,
-                      int k0, double* dst) -> unsigned {
-    unsigned m = 0;
+  // fixed per-thread byte offset plus r times a uniform stride (the planner
+  // keeps every operand below 2^28 elements, so a real offset stays below
+  // 2^31 - 8), and a range check is one compare.
+  auto fetch_op = [&](const double* base, int lead_major, int ld, int lo, int hi, int g0, int kp, int k0,
+                      double* dst) {
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)0x80000000u, 0x00020000);
     if (lead_major) {
       const int gi = g0 + (tid & (GT - 1));
       const bool iok = unsigned(gi - lo) < unsigned(hi - lo);
       const int kb = k0 + (tid >> 6);
-      const unsigned off0 = (unsigned(iok ? gi - lo : 0) + unsigned(kb) * unsigned(ld)) * 8u;
+      const unsigned off0 = (unsigned(gi - lo) + unsigned(kb) * unsigned(ld)) * 8u;
       const unsigned step = 32u * unsigned(ld);
 #pragma unroll
       for (int r = 0; r < GR; ++r) {
         const bool ok = iok && kb + 4 * r < kp;
-        const unsigned off = ok ? off0 + unsigned(r) * step : 0u;
-        dst[r] = *(const HC_GLOBAL double*)(base + off);
-        m |= unsigned(ok) << r;
+        const unsigned off = ok ? off0 + unsigned(r) * step : 0x80000000u;
+        dst[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
       }
     } else {
       const int gk = k0 + (tid & (GK - 1));
@@ -117,24 +126,17 @@ __device__ __forceinline__ void gemm_products(const Bufs* __restrict__ bufs, con
 #pragma unroll
       for (int r = 0; r < GR; ++r) {
         const bool ok = kok && unsigned(ib + 8 * r) < unsigned(hi - lo);
-        const unsigned off = ok ? off0 + unsigned(r) * step : 0u;
-        dst[r] = *(const HC_GLOBAL double*)(base + off);
-        m |= unsigned(ok) << r;
+        const unsigned off = ok ? off0 + unsigned(r) * step : 0x80000000u;
+        dst[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
       }
     }
-    return m;
   };
   auto fetch = [&](const ProdMeta& M, int k0) {
-    // descriptor fields are the same in every lane: scalar registers, so
-    // that the operand layout is one uniform branch and the loads take a
-    // scalar base address
-    const HC_GLOBAL char* MA = (const HC_GLOBAL char*)gmem(uniform_ptr(M.A));
-    const HC_GLOBAL char* MB = (const HC_GLOBAL char*)gmem(uniform_ptr(M.B));
     const int kp = uniform_int(M.k);
-    ma = fetch_op(MA, uniform_int(M.ta) == 0, uniform_int(M.lda), uniform_int(M.pr0), uniform_int(M.pr1), r0, kp,
-                  k0, ra);
-    mb = fetch_op(MB, uniform_int(M.tb) == 1, uniform_int(M.ldb), uniform_int(M.pc0), uniform_int(M.pc1), c0, kp,
-                  k0, rb);
+    fetch_op(uniform_ptr(M.A), uniform_int(M.ta) == 0, uniform_int(M.lda), uniform_int(M.pr0), uniform_int(M.pr1),
+             r0, kp, k0, ra);
+    fetch_op(uniform_ptr(M.B), uniform_int(M.tb) == 1, uniform_int(M.ldb), uniform_int(M.pc0), uniform_int(M.pc1),
+             c0, kp, k0, rb);
   };
   const ProdMeta* pmc = pm;
   auto stash = [&](const ProdMeta& M) {
@@ -147,26 +149,32 @@ __device__ __forceinline__ void gemm_products(const Bufs* __restrict__ bufs, con
     // [tid % 32][tid / 32 + 8 r]: a per-thread base and an immediate offset
     const int lead0 = (tid >> 6) * (GT + 1) + (tid & (GT - 1));
     const int kmaj0 = (tid & (GK - 1)) * (GT + 1) + (tid >> 5);
+    if (alpha != 1.0) {
+#pragma unroll
+      for (int r = 0; r < GR; ++r) ra[r] *= alpha;
+    }
     if (ta == 0) {
 #pragma unroll
-      for (int r = 0; r < GR; ++r) Af[lead0 + 4 * r * (GT + 1)] = T(((ma >> r) & 1u) ? alpha * ra[r] : 0.0);
+      for (int r = 0; r < GR; ++r) Af[lead0 + 4 * r * (GT + 1)] = T(ra[r]);
     } else {
 #pragma unroll
-      for (int r = 0; r < GR; ++r) Af[kmaj0 + 8 * r] = T(((ma >> r) & 1u) ? alpha * ra[r] : 0.0);
+      for (int r = 0; r < GR; ++r) Af[kmaj0 + 8 * r] = T(ra[r]);
     }
     if (tb == 1) {
 #pragma unroll
-      for (int r = 0; r < GR; ++r) Bf[lead0 + 4 * r * (GT + 1)] = T(((mb >> r) & 1u) ? rb[r] : 0.0);
+      for (int r = 0; r < GR; ++r) Bf[lead0 + 4 * r * (GT + 1)] = T(rb[r]);
     } else {
 #pragma unroll
-      for (int r = 0; r < GR; ++r) Bf[kmaj0 + 8 * r] = T(((mb >> r) & 1u) ? rb[r] : 0.0);
+      for (int r = 0; r < GR; ++r) Bf[kmaj0 + 8 * r] = T(rb[r]);
     }
   };
 
+  // pairs and additions of the earlier batches, modulo G
+  int gpair = 0, gadd = 0;
   for (int base = J.p0; base < J.p1; base += PBATCH) {
     const int cnt = min(PBATCH, J.p1 - base);
     __syncthreads();   // the previous batch is consumed
-    if (tid < cnt) {
+    if (grp == 0 && tid < cnt) {
       const GemmProd Pd = prods[base + tid];
       ProdMeta M;
       M.k = dimv(dyn, Pd.k);
@@ -195,29 +203,77 @@ __device__ __forceinline__ void gemm_products(const Bufs* __restrict__ bufs, con
       is_add = M.live && M.tb == 2;
     }
     const unsigned long long prod_mask = __ballot(is_prod), add_mask = __ballot(is_add);
-    for (unsigned long long am = add_mask; am != 0ull; am &= am - 1ull) on_add(pmc[__ffsll((long long)am) - 1]);
+    for (unsigned long long am = add_mask; am != 0ull; am &= am - 1ull) {
+      if (gadd == grp) on_add(pmc[__ffsll((long long)am) - 1]);
+      if (G > 1) gadd = gadd + 1 == G ? 0 : gadd + 1;
+    }
     // products: (product, k-chunk) pairs in order
     auto next_live = [&](int q) {
       const unsigned long long rest = q < 64 ? prod_mask & (~0ull << q) : 0ull;
       return rest != 0ull ? __ffsll((long long)rest) - 1 : cnt;
     };
-    int q = next_live(0);
-    if (q >= cnt) continue;
-    int k0 = 0;
-    fetch(pmc[q], 0);
-    while (q < cnt) {
-      if (k0 > 0 || q > 0) __syncthreads();   // LDS tiles of the previous pair consumed
-      stash(pmc[q]);
-      __syncthreads();
-      int nq = q, nk0 = k0 + GK;
-      if (nk0 >= pmc[q].k) {
-        nq = next_live(q + 1);
-        nk0 = 0;
+    if constexpr (G == 1) {
+      int q = next_live(0);
+      if (q >= cnt) continue;
+      int k0 = 0;
+      fetch(pmc[q], 0);
+      while (q < cnt) {
+        if (k0 > 0 || q > 0) __syncthreads();   // LDS tiles of the previous pair consumed
+        stash(pmc[q]);
+        __syncthreads();
+        int nq = q, nk0 = k0 + GK;
+        if (nk0 >= pmc[q].k) {
+          nq = next_live(q + 1);
+          nk0 = 0;
+        }
+        if (nq < cnt) fetch(pmc[nq], nk0);
+        on_chunk(min(GK, pmc[q].k - k0));
+        q = nq;
+        k0 = nk0;
       }
-      if (nq < cnt) fetch(pmc[nq], nk0);
-      on_chunk(min(GK, pmc[q].k - k0));
-      q = nq;
-      k0 = nk0;
+    } else {
+      // (q, k0) moved d pairs on over the live products of the batch
+      auto advance = [&](int& q, int& k0, int d) {
+        while (q < cnt) {
+          const int left = (uniform_int(pmc[q].k) - k0 + GK - 1) / GK;   // pairs from (q, k0) to the end of q
+          if (d < left) {
+            k0 += d * GK;
+            return;
+          }
+          d -= left;
+          q = next_live(q + 1);
+          k0 = 0;
+        }
+      };
+      int total = 0;
+      for (unsigned long long pmk = prod_mask; pmk != 0ull; pmk &= pmk - 1ull)
+        total += (uniform_int(pmc[__ffsll((long long)pmk) - 1].k) + GK - 1) / GK;
+      int q = next_live(0), k0 = 0;
+      advance(q, k0, grp >= gpair ? grp - gpair : grp - gpair + G);
+      gpair = (gpair + total) % G;
+      // rounds of the batch: every group stashes and consumes one pair per
+      // round; a group without a pair left takes a chunk of the batch's
+      // first live product and consumes none of it (no branches
+      // around the pipeline, which keeps its registers as in the plain kernel)
+      const int rounds = (total + G - 1) / G;
+      if (rounds == 0) continue;
+      const int qfirst = next_live(0);
+      fetch(pmc[q < cnt ? q : qfirst], q < cnt ? k0 : 0);
+      for (int rd = 0; rd < rounds; ++rd) {
+        if (rd > 0) __syncthreads();   // LDS tiles of the previous round consumed
+        const bool real = q < cnt;
+        stash(pmc[real ? q : qfirst]);
+        __syncthreads();
+        int nq = q, nk0 = k0, kl = 0;
+        if (real) {
+          kl = min(GK, uniform_int(pmc[q].k) - k0);
+          advance(nq, nk0, G);
+        }
+        fetch(pmc[nq < cnt ? nq : qfirst], nq < cnt ? nk0 : 0);
+        on_chunk(kl);
+        q = nq;
+        k0 = nk0;
+      }
     }
   }
 }
@@ -283,17 +339,56 @@ __device__ __forceinline__ void gemm_tile(const Bufs* __restrict__ bufs, const i
 // computing the transposed block, D' = B^T A^T, so that lane L holds the
 // element (row L % 16, column 4 r + L / 16) of the block in its register r:
 // sixteen consecutive rows of a column, a coalesced store.
+//
+// With G groups (gemm_products) each group runs this body on its own chunk
+// buffers; at the end groups 1 .. G-1 hand their sums to group 0 through
+// LDS (xred, 16 x 256 (G - 1) doubles), which adds them in group order and
+// writes C.
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// The k steps of one chunk for a wave holding NB blocks of one block row
+// bi, in block columns bj0, bj0 + STRIDE, ...: step s (s = kpart, kpart +
+// NSPLIT, ... < ns) multiplies rows 4 s .. 4 s + 3 of the chunk.  Every
+// operand sits at a compile-time offset from two per-lane bases, so the
+// loop is fully unrolled with no address arithmetic, and its LDS reads do
+// not depend on the step guard (rows past the chunk's k are zero and in
+// the buffer), so they can be issued ahead of the matrix instructions.
+template <int NB, int STRIDE, int NSPLIT>
+__device__ __forceinline__ void mfma_chunk(const double (*As)[GT + 1], const double (*Bs)[GT + 1], dbl4* acc,
+                                           int bi, int bj0, int li, int lk, int kpart, int ns) {
+  constexpr int NS = GK / 4 / NSPLIT;
+  constexpr int ROW = 4 * NSPLIT * (GT + 1);
+  const double* __restrict__ pa = &As[4 * kpart + lk][16 * bi + li];
+  const double* __restrict__ pb = &Bs[4 * kpart + lk][16 * bj0 + li];
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    const double a = pa[i * ROW];
+    double b[NB];
+#pragma unroll
+    for (int t = 0; t < NB; ++t) b[t] = pb[i * ROW + 16 * STRIDE * t];
+    if (kpart + i * NSPLIT < ns) {
+#pragma unroll
+      for (int t = 0; t < NB; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(b[t], a, acc[t], 0, 0, 0);
+    }
+  }
+}
+
+template <int G = 1>
 __device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
                                                const GemmJob& J, const GemmProd* __restrict__ prods, int m,
                                                int n, int r0, int c0, double (*As)[GT + 1], double (*Bs)[GT + 1],
-                                               ProdMeta* pm) {
-  const int tid = threadIdx.x, wave = uniform_int(tid >> 6), lane = tid & 63;
+                                               ProdMeta* pm, double* xred = nullptr) {
+  const int tid = threadIdx.x & 255, wave = uniform_int(tid >> 6), lane = tid & 63;
+  const int grp = G > 1 ? uniform_int(int(threadIdx.x >> 8)) : 0;
   const int li = lane & 15, lk = lane >> 4;
   const int er = min(GT, m - r0), ec = min(GT, n - c0);
   const int nbr = (er + 15) >> 4, nbc = (ec + 15) >> 4, nblk = nbr * nbc;
   const int nsplit = nblk == 1 ? 4 : (nblk == 2 ? 2 : 1);
-  int kpart = 0, nb = 0;
+  // blocks of a wave: one block row bi and nb block columns bj[t] = bj[0] +
+  // stride t (16 x 16 blocks of the tile; a wave without blocks only joins
+  // the barriers); a tile of one or two blocks splits their k steps over
+  // nsplit waves instead
+  int kpart = 0, nb = 0, stride = 1;
   int bi[4] = {0, 0, 0, 0}, bj[4] = {0, 0, 0, 0};
   if (nsplit > 1) {
     const int b = wave / nsplit;
@@ -301,16 +396,22 @@ __device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, co
     nb = 1;
     bi[0] = b % nbr;
     bj[0] = b / nbr;
+  } else if (nbr >= 3) {
+    nb = wave < nbr ? nbc : 0;
+    bi[0] = wave;
+  } else if (nbr == 2) {
+    bi[0] = wave & 1;
+    bj[0] = wave >> 1;
+    nb = (nbc - bj[0] + 1) >> 1;
+    stride = 2;
   } else {
+    nb = wave < nbc ? 1 : 0;
+    bj[0] = wave;
+  }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int b = wave + 4 * t;
-      if (b < nblk) {
-        bi[t] = b % nbr;
-        bj[t] = b / nbr;
-        nb = t + 1;
-      }
-    }
+  for (int t = 1; t < 4; ++t) {
+    bi[t] = bi[0];
+    bj[t] = bj[0] + stride * t;
   }
   dbl4 acc[4];
 #pragma unroll
@@ -332,19 +433,26 @@ __device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, co
   };
   auto on_chunk = [&](int kl) {
     const int ns = (kl + 3) >> 2;
-    for (int s = kpart; s < ns; s += nsplit) {
-      const int kr = 4 * s + lk;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        if (t < nb) {
-          const double av = Bs[kr][16 * bj[t] + li];
-          const double bv = As[kr][16 * bi[t] + li];
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
-        }
+    if (nsplit == 4) {
+      mfma_chunk<1, 1, 4>(As, Bs, acc, bi[0], bj[0], li, lk, kpart, ns);
+    } else if (nsplit == 2) {
+      mfma_chunk<1, 1, 2>(As, Bs, acc, bi[0], bj[0], li, lk, kpart, ns);
+    } else if (stride == 2) {
+      if (nb == 2)
+        mfma_chunk<2, 2, 1>(As, Bs, acc, bi[0], bj[0], li, lk, 0, ns);
+      else if (nb == 1)
+        mfma_chunk<1, 1, 1>(As, Bs, acc, bi[0], bj[0], li, lk, 0, ns);
+    } else {
+      switch (nb) {
+        case 4: mfma_chunk<4, 1, 1>(As, Bs, acc, bi[0], bj[0], li, lk, 0, ns); break;
+        case 3: mfma_chunk<3, 1, 1>(As, Bs, acc, bi[0], bj[0], li, lk, 0, ns); break;
+        case 2: mfma_chunk<2, 1, 1>(As, Bs, acc, bi[0], bj[0], li, lk, 0, ns); break;
+        case 1: mfma_chunk<1, 1, 1>(As, Bs, acc, bi[0], bj[0], li, lk, 0, ns); break;
+        default: break;
       }
     }
   };
-  gemm_products<double>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm, on_add, on_chunk);
+  gemm_products<double, G>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm, on_add, on_chunk);
   if (nsplit > 1) {
     // partial sums of the k split: waves with kpart > 0 hand theirs over
     double* red = &As[0][0];
@@ -358,6 +466,29 @@ __device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, co
       for (int w = 1; w < nsplit; ++w) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[0][r] += red[((wave + w) * 4 + r) * 64 + lane];
+      }
+    }
+  }
+  if constexpr (G > 1) {
+    __syncthreads();   // every group's chunk buffers are free
+    if (grp > 0 && kpart == 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xred[((grp - 1) * 16 + 4 * t + r) * 256 + tid] = acc[t][r];
+        }
+    }
+    __syncthreads();
+    if (grp > 0) return;
+    if (kpart == 0) {
+      for (int g = 1; g < G; ++g) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < nb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[t][r] += xred[((g - 1) * 16 + 4 * t + r) * 256 + tid];
+          }
       }
     }
   }
@@ -380,10 +511,11 @@ __device__ __forceinline__ void gemm_tile_mfma(const Bufs* __restrict__ bufs, co
   }
 }
 
-// Four work-groups per CU (at most 128 registers a lane): the LDS chunks
-// fit four times, and the fourth work-group hides more of each tile's
-// operand-load latency than the registers it costs.
-__global__ __launch_bounds__(256, 4) void k_gemm(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
+// Two work-groups per CU (up to 256 registers a lane): the chunk loop keeps
+// the next chunk's loads and the LDS operands of the coming k steps in
+// registers, which costs more than the latency a third or fourth
+// work-group would hide.
+__global__ __launch_bounds__(256, 2) void k_gemm(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
                                               const GemmJob* __restrict__ jobs,
                                               const GemmProd* __restrict__ prods,
                                               const GemmTile* __restrict__ tiles, int t0) {
@@ -415,6 +547,31 @@ __global__ __launch_bounds__(256, 4) void k_gemm(const Bufs* __restrict__ bufs, 
     return;
   }
   gemm_tile_mfma(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm);
+}
+
+// One tile per work-group of GW groups of 256 threads (FP64 jobs only): the
+// groups stream disjoint pairs of the tile in lockstep (gemm_products), so a
+// tile with many k chunks takes about 1 / GW of the chunk rounds of k_gemm.
+// A CU holds one such work-group; the planner uses this kernel for launches
+// whose longest tiles, not their number, set the time.
+constexpr int GW = GEMM_GROUPS;
+constexpr size_t LDS_GEMM_WIDE = size_t(GW) * 2 * GK * (GT + 1) * 8;
+static_assert(size_t(GW - 1) * 16 * 256 * 8 <= LDS_GEMM_WIDE, "group sums fit in the chunk buffers");
+__global__ __launch_bounds__(256 * GW) void k_gemm_wide(const Bufs* __restrict__ bufs, const int* __restrict__ dyn,
+                                                      const GemmJob* __restrict__ jobs,
+                                                      const GemmProd* __restrict__ prods,
+                                                      const GemmTile* __restrict__ tiles, int t0) {
+  const GemmTile T = tiles[t0 + blockIdx.x];
+  const GemmJob J = jobs[T.job];
+  const int m = dimv(dyn, J.m), n = dimv(dyn, J.n);
+  const int r0 = T.ti * GT, c0 = T.tj * GT;
+  if (r0 >= m || c0 >= n) return;
+  extern __shared__ double smem[];
+  __shared__ ProdMeta pm[PBATCH];
+  const int grp = int(threadIdx.x >> 8);
+  double(*As)[GT + 1] = reinterpret_cast<double(*)[GT + 1]>(smem + size_t(grp) * 2 * GK * (GT + 1));
+  double(*Bs)[GT + 1] = reinterpret_cast<double(*)[GT + 1]>(smem + size_t(grp) * 2 * GK * (GT + 1) + GK * (GT + 1));
+  gemm_tile_mfma<GW>(bufs, dyn, J, prods, m, n, r0, c0, As, Bs, pm, smem);
 }
 
 // ------------------------------------------------------------------ TSQR
@@ -2550,6 +2707,8 @@ hipError_t setup_kernel_attributes() {
   e = hipFuncSetAttribute((const void*)k_trsm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_TRSM);
   if (e != hipSuccess) return e;
   e = hipFuncSetAttribute((const void*)k_trmm, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_TRSM);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_gemm_wide, hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_GEMM_WIDE);
   return e;
 }
 
@@ -2558,6 +2717,10 @@ hipError_t launch_stage(const Stage& s, const LaunchCtx& L, hipStream_t st) {
   switch (s.kind) {
     case ST_GEMM:
       if (n > 0) k_gemm<<<n, 256, 0, st>>>(L.dbufs, L.dyn, L.gjobs, L.gprods, L.gtiles, s.begin);
+      break;
+    case ST_GEMM_WIDE:
+      if (n > 0)
+        k_gemm_wide<<<n, 256 * GW, LDS_GEMM_WIDE, st>>>(L.dbufs, L.dyn, L.gjobs, L.gprods, L.gtiles, s.begin);
       break;
     case ST_TSQR_SEG:
       if (n > 0) k_tsqr_seg<<<n, 256, LDS_QR, st>>>(L.dbufs, L.dyn, L.tsegs, s.begin, L.rmax);

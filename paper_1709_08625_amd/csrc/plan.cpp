@@ -175,21 +175,31 @@ class Builder {
     int32_t t0 = int32_t(P.gtiles.size());
     // estimated k chunks per tile, accumulated over the tiles each product spans
     std::vector<int> tcost;
+    // the grouped kernel adds a tile's chunks in another order: launches with
+    // a solve job keep the plain kernel, so that the sweep's fused solve and
+    // the stand-alone forward solve do the same arithmetic; FP32 jobs need
+    // the vector body of the plain kernel
+    bool wide_ok = true;
     for (int32_t j = 0; j < nj; ++j) {
       GemmJob& g = P.gjobs[job_base + j];
       g.p0 = int32_t(P.gprods.size());
       const int mt = (g.m.maxv + TM - 1) / TM, nt = (g.n.maxv + TN - 1) / TN;
       const size_t tb = tcost.size();
       tcost.resize(tb + size_t(mt) * nt, 0);
+      if (g.C.buf == B_RHS) wide_ok = false;
       for (auto& p : pending_prods[j]) {
         P.gprods.push_back(p);
-        if (p.A.buf == B_RHS || p.B.buf == B_RHS) g.fp32 = 0;   // the solve stays FP64
+        if (p.A.buf == B_RHS || p.B.buf == B_RHS) {
+          g.fp32 = 0;   // the solve stays FP64
+          wide_ok = false;
+        }
         const int c = p.tb == 2 ? 1 : chunks(est_k(p.k));
         const int a0 = std::max(0, p.i0 / TM), a1 = std::min(mt, (p.i0 + p.mi.maxv + TM - 1) / TM);
         const int b0 = std::max(0, p.j0 / TN), b1 = std::min(nt, (p.j0 + p.nj.maxv + TN - 1) / TN);
         for (int a = a0; a < a1; ++a)
           for (int b = b0; b < b1; ++b) tcost[tb + size_t(a) * nt + b] += c;
       }
+      if (g.fp32) wide_ok = false;
       g.p1 = int32_t(P.gprods.size());
       for (int a = 0; a < mt; ++a)
         for (int b = 0; b < nt; ++b) P.gtiles.push_back(GemmTile{job_base + j, a, b, 0});
@@ -209,7 +219,20 @@ class Builder {
       sorted.reserve(cost.size());
       for (auto& ct : cost) sorted.push_back(P.gtiles[ct.second]);
       std::copy(sorted.begin(), sorted.end(), P.gtiles.begin() + t0);
-      out.push_back(Stage{ST_GEMM, t0, t1, cur_lane});
+      // chunk times of the launch, heaviest first: the plain kernel runs 4
+      // tiles per CU, each through its chunks one by one; the grouped one
+      // runs 1 tile per CU, GEMM_GROUPS chunks of it at a time
+      int64_t plain_tot = 0, wide_tot = 0;
+      int cmax = 0;
+      for (auto& ct : cost) {
+        const int c = -ct.first;
+        cmax = std::max(cmax, c);
+        plain_tot += c;
+        wide_tot += (c + GEMM_GROUPS - 1) / GEMM_GROUPS;
+      }
+      const int64_t plain = std::max<int64_t>(cmax, (plain_tot + 1023) / 1024);
+      const int64_t wide = std::max<int64_t>((cmax + GEMM_GROUPS - 1) / GEMM_GROUPS, (wide_tot + 255) / 256);
+      out.push_back(Stage{wide_ok && wide < plain ? ST_GEMM_WIDE : ST_GEMM, t0, t1, cur_lane});
     }
   }
 
@@ -1318,14 +1341,14 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
   Bd.build_solves();
   Bd.build_matvec();
   if (Bd.dyn_max > P.n_dyn) P.n_dyn = Bd.dyn_max;
-  // the GEMM kernel addresses an element of a product operand by a 32-bit
-  // byte offset from the operand's start
+  // the GEMM kernel addresses an element of a product operand by a byte
+  // offset below 2^31 from the operand's start, 2^31 being its masked one
   for (const GemmProd& g : P.gprods) {
     if (g.tb == 2) continue;
     const int64_t kk = g.k.maxv, mi = g.mi.maxv, nj = g.nj.maxv;
     const int64_t a = g.ta == 0 ? mi + kk * g.A.ld : kk + mi * g.A.ld;
     const int64_t b = g.tb == 0 ? kk + nj * g.B.ld : nj + kk * g.B.ld;
-    if (std::max(a, b) >= (int64_t(1) << 29)) return "a GEMM operand spans 2^29 elements or more";
+    if (std::max(a, b) >= (int64_t(1) << 28)) return "a GEMM operand spans 2^28 elements or more";
   }
   int64_t launches = 0;
   for (auto& s : P.steps)

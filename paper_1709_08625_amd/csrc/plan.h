@@ -141,8 +141,11 @@ struct TrsmJob {
 // ---------------------------------------------------------------- stages
 // ST_FORK: the second lane (stream) waits for the work issued so far on the
 // first; ST_JOIN: the first lane waits for the work issued on the second.
+// ST_GEMM_WIDE: the same tiles as ST_GEMM, run by the grouped kernel (four
+// groups of 256 threads per tile) for launches bound by their longest tile.
+constexpr int GEMM_GROUPS = 2;   // groups of 256 threads of the grouped GEMM kernel
 enum StageKind : int32_t { ST_GEMM = 0, ST_TSQR_SEG, ST_TSQR_RED, ST_SMALL, ST_LEAF, ST_TRSM, ST_COPY_RANK,
-                           ST_FORK, ST_JOIN, ST_TRMM };
+                           ST_FORK, ST_JOIN, ST_TRMM, ST_GEMM_WIDE };
 struct Stage {
   int32_t kind;
   int32_t begin, end;   // item range in the kind's array (tiles for GEMM)
