@@ -111,3 +111,60 @@ def test_resident_dataset_matches_context():
         assert (r["loglik"], r["logdet"], r["quad"]) == (ll, ld, q)
     for (l, zz, th), r in zip(other, res2):
         assert (r["loglik"], r["logdet"], r["quad"]) == _alone(l, zz, th, eps, leaf, eta)
+
+
+# ------------------------------------------------------------------ failures
+def test_poisoned_request_fails_alone():
+    # one request in the mix has two coincident locations and no nugget (an
+    # exactly singular C: Sec. 3 names duplicate locations as the cause of a
+    # failing factorisation); it reports HCOV_ENOTSPD while every other
+    # request of the mix returns what it returns alone, bit for bit
+    eps, leaf, eta = 1e-8, 64, 2.0
+    reqs = _requests(5, seed=13, n_hi=3000)
+    locs, z = workloads.uniform(1500, seed=77)
+    locs[40] = locs[7]
+    bad = (locs, z, (1.0, 0.1, 0.5, 0.0))
+    mix = reqs[:2] + [bad] + reqs[2:]
+    alone = [_alone(l, zz, th, eps, leaf, eta) for l, zz, th in reqs]
+    S = hcov.Server(slots=3)
+    try:
+        tickets = [S.submit(zz, th, locs=l, eps=eps, leaf=leaf, eta=eta) for l, zz, th in mix]
+        res = [S.wait(t) for t in tickets]
+    finally:
+        S.close()
+    assert res[2]["status"] == hcov.ENOTSPD
+    good = res[:2] + res[3:]
+    for (ll, ld, q), r in zip(alone, good):
+        assert r["status"] == 0
+        assert (r["loglik"], r["logdet"], r["quad"]) == (ll, ld, q)
+
+
+def test_memory_cap_rejects_only_what_exceeds_it():
+    # opts.mem_cap_bytes: a build whose planned device memory exceeds the cap
+    # fails with HCOV_ENOMEM before it allocates; below the cap it runs.  The
+    # cap is set between the footprints of a small and a large request, and
+    # the server applies it per request
+    eps, leaf, eta = 1e-8, 64, 2.0
+    small = _requests(1, seed=21, n_lo=900, n_hi=901)[0]
+    large = _requests(1, seed=22, n_lo=12000, n_hi=12001)[0]
+    foot = []
+    for l, zz, th in (small, large):
+        H = hcov.HCov(l, th, eps=eps, leaf=leaf, eta=eta)
+        try:
+            foot.append(H.stats()["bytes_device"])
+        finally:
+            H.close()
+    assert foot[1] > 4 * foot[0]
+    cap = 2 * foot[0]
+    with pytest.raises(hcov.HcovError) as e:
+        hcov.HCov(large[0], large[2], eps=eps, leaf=leaf, eta=eta, opts={"mem_cap_bytes": cap})
+    assert e.value.code == hcov.ENOMEM
+    S = hcov.Server(slots=2, opts={"mem_cap_bytes": cap})
+    try:
+        t = [S.submit(zz, th, locs=l, eps=eps, leaf=leaf, eta=eta) for l, zz, th in (small, large)]
+        r = [S.wait(x) for x in t]
+    finally:
+        S.close()
+    assert r[0]["status"] == 0
+    assert (r[0]["loglik"], r[0]["logdet"], r[0]["quad"]) == _alone(*small, eps, leaf, eta)
+    assert r[1]["status"] == hcov.ENOMEM
