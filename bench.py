@@ -86,14 +86,17 @@ def cpu_baseline(n_full, theta, sizes=(1000, 2000, 4000)):
 
 def serving(args, hcov, workloads):
     """Serving stream: requests of n log-uniform in [1k, 64k], uniform
-    locations, theta uniform in the stated boxes, z = xi (FP64, eps 1e-7,
-    leaf 64, eta 2, nugget 1e-4).  A request whose blocks need more than the
-    rank capacity (HCOV_ERANK: the smoothest kernels of the box, nu near 2.5
-    with ell near 0.3) fails alone and is counted, not retried.  Three runs of the same requests: the plain
+    locations, theta uniform in the stated boxes, z = xi (FP64, eps 1e-8,
+    leaf 64, eta 2, nugget 1e-4).  A request whose factorisation cannot reach
+    the accuracy within the rank capacity (HCOV_ERANK) or loses positive
+    definiteness (HCOV_ENOTSPD) fails alone and is counted, not retried: the
+    smoothest, worst-conditioned kernels of the box (nu near 2.5 with large
+    ell), where the truncation errors of the Schur complements are amplified
+    by the condition number.  Three runs of the same requests: the plain
     path one at a time in arrival order (FIFO), the server with every request
     queued at once (capacity), and the server under Poisson arrivals at 0.8 x
     its own capacity (latency under load)."""
-    eps, leaf, eta, nug = 1e-7, 64, 2.0, 1e-4
+    eps, leaf, eta, nug = 1e-8, 64, 2.0, 1e-4
     reqs = workloads.serving_stream(count=args.requests, seed=0, rate=1.0)
     inputs = [workloads.request_inputs(r) for r in reqs]
     thetas = [(r["sigma2"], r["ell"], r["nu"], nug) for r in reqs]
@@ -122,7 +125,7 @@ def serving(args, hcov, workloads):
         wall = time.perf_counter() - t0
         S.close()
         bad = [r["status"] for r in res if r["status"] != 0]
-        assert all(b == hcov.ERANK for b in bad), bad
+        assert all(b in (hcov.ERANK, hcov.ENOTSPD) for b in bad), bad
         lat = np.array([r["latency_ms"] for r in res])
         return wall, lat, res
 
@@ -154,9 +157,11 @@ def serving(args, hcov, workloads):
         "open_loop": {"arrival_rate_per_s": rate, "evals_per_s": len(reqs) / t_open, "p50_ms": pct(lat_open, 50),
                       "p99_ms": pct(lat_open, 99)},
         "results_identical_across_runs": bool(same),
-        "failed_erank": {"count": len(failed),
-                         "theta": [[round(v, 4) for v in thetas[i][:3]] for i in failed],
-                         "n": [int(len(inputs[i][1])) for i in failed]},
+        "failed": {"count": len(failed),
+                   "erank": sum(res_cap[i]["status"] == hcov.ERANK for i in failed),
+                   "enotspd": sum(res_cap[i]["status"] == hcov.ENOTSPD for i in failed),
+                   "theta": [[round(v, 4) for v in thetas[i][:3]] for i in failed],
+                   "n": [int(len(inputs[i][1])) for i in failed]},
     }
 
 

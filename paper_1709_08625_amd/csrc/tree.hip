@@ -4,10 +4,10 @@
 // axis-parallel cut across the longer side of the cluster's bounding box.
 // Level-synchronous: at each level every node's points are ordered by
 // (coordinate on the node's split axis, original index) with one device-wide
-// radix sort of the 64-bit key (node << 32 | rank on that axis), where the
-// rank of a point on an axis is its position in the global order
-// (coordinate, index); the first ceil(s/2) points of a node form its left
-// son.  Leaves are finally ordered by original index.  Bounding boxes are
+// radix sort (the library's own, below) of the 64-bit key (node << 32 | rank
+// on that axis), where the rank of a point on an axis is its position in the
+// global order (coordinate, index); the first ceil(s/2) points of a node form
+// its left son.  Leaves are finally ordered by original index.  Bounding boxes are
 // exact min/max reductions, so the result is bit-identical to the CPU
 // reference.
 //
@@ -17,7 +17,6 @@
 // single IEEE operations, no contraction), a dense leaf at the leaf level,
 // otherwise it is replaced by its son pairs.
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
 
 #include <cstdint>
 #include <string>
@@ -213,6 +212,188 @@ __global__ void k_expand(const int2* __restrict__ fr, int cnt, const int* __rest
 
 static int nblk(int64_t n, int b) { return (int)((n + b - 1) / b); }
 
+// ------------------------------------------------------------------ scan
+// Exclusive prefix sum of unsigned 32-bit counts: each work-group scans 1024
+// entries (4 a thread, the thread totals scanned by shuffles inside a wave
+// and through LDS across the four waves) and writes its total; the totals
+// are scanned the same way (recursively) and added back.
+constexpr int SC_THREADS = 256, SC_ITEMS = 4, SC_TILE = SC_THREADS * SC_ITEMS;
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_tile(const unsigned* __restrict__ in, unsigned* __restrict__ out,
+                                                          int64_t n, unsigned* __restrict__ totals) {
+  __shared__ unsigned wsum[SC_THREADS / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t base = int64_t(blockIdx.x) * SC_TILE + int64_t(tid) * SC_ITEMS;
+  unsigned v[SC_ITEMS], t = 0;
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0u;
+    t += v[i];
+  }
+  // inclusive scan of the thread totals inside the wave
+  unsigned x = t;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  unsigned before = x - t;
+  for (int w = 0; w < wave; ++w) before += wsum[w];
+#pragma unroll
+  for (int i = 0; i < SC_ITEMS; ++i) {
+    if (base + i < n) out[base + i] = before;
+    before += v[i];
+  }
+  if (totals && tid == SC_THREADS - 1) totals[blockIdx.x] = before;
+}
+
+__global__ __launch_bounds__(SC_THREADS) void k_scan_add(unsigned* __restrict__ out, int64_t n,
+                                                         const unsigned* __restrict__ offs) {
+  const int64_t i = int64_t(blockIdx.x) * SC_TILE + threadIdx.x;
+  const unsigned a = offs[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < SC_ITEMS; ++k)
+    if (i + k * SC_THREADS < n) out[i + k * SC_THREADS] += a;
+}
+
+// Scratch (unsigned entries) that exclusive_sum needs for n entries.
+static int64_t scan_scratch(int64_t n) {
+  const int64_t nb = nblk(n, SC_TILE);
+  return nb > 1 ? 2 * nb + scan_scratch(nb) : 1;
+}
+
+// out[i] = in[0] + ... + in[i-1] for i < n (in and out may not alias);
+// scratch holds scan_scratch(n) entries.
+static std::string exclusive_sum(const unsigned* in, unsigned* out, int64_t n, unsigned* scratch, hipStream_t st) {
+  if (n <= 0) return "";
+  const int nb = nblk(n, SC_TILE);
+  if (nb == 1) {
+    k_scan_tile<<<1, SC_THREADS, 0, st>>>(in, out, n, nullptr);
+    TCHK(hipGetLastError());
+    return "";
+  }
+  unsigned* totals = scratch;
+  k_scan_tile<<<nb, SC_THREADS, 0, st>>>(in, out, n, totals);
+  TCHK(hipGetLastError());
+  // the totals are scanned in place through the rest of the scratch
+  unsigned* sums = scratch + nb;
+  std::string e = exclusive_sum(totals, sums, nb, sums + nb, st);
+  if (!e.empty()) return e;
+  k_scan_add<<<nb, SC_THREADS, 0, st>>>(out, n, sums);
+  TCHK(hipGetLastError());
+  return "";
+}
+
+// ------------------------------------------------------------------ sort
+// Stable least-significant-digit radix sort of (64-bit key, 32-bit value)
+// pairs on the bits [0, endbit) of the key, 8 bits a pass.  A pass counts
+// the digits of each tile of 2048 keys (digit-major table: digit d of tile
+// b at d * tiles + b), scans the table, and scatters: inside a tile the
+// keys go in index order, a key's position among the earlier keys of its
+// digit coming from the wave (ballots of the digit's bits: the lanes with
+// the same digit, and the rank among them), the earlier waves of the same
+// round (per-wave digit counts in LDS) and the earlier rounds (a running
+// count per digit).
+constexpr int RS_THREADS = 256, RS_ITEMS = 8, RS_TILE = RS_THREADS * RS_ITEMS, RS_BINS = 256;
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_count(const unsigned long long* __restrict__ keys, int64_t n,
+                                                         int shift, int tiles, unsigned* __restrict__ table) {
+  __shared__ unsigned cnt[RS_BINS];
+  const int tid = threadIdx.x;
+  cnt[tid] = 0u;
+  __syncthreads();
+  const int64_t base = int64_t(blockIdx.x) * RS_TILE;
+#pragma unroll
+  for (int i = 0; i < RS_ITEMS; ++i) {
+    const int64_t idx = base + i * RS_THREADS + tid;
+    if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 0xff], 1u);
+  }
+  __syncthreads();
+  table[int64_t(tid) * tiles + blockIdx.x] = cnt[tid];
+}
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const unsigned long long* __restrict__ kin,
+                                                           const int* __restrict__ vin, int64_t n, int shift,
+                                                           int tiles, const unsigned* __restrict__ offs,
+                                                           unsigned long long* __restrict__ kout,
+                                                           int* __restrict__ vout) {
+  __shared__ unsigned run[RS_BINS];
+  __shared__ unsigned wcnt[RS_THREADS / 64][RS_BINS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  run[tid] = offs[int64_t(tid) * tiles + blockIdx.x];
+  const unsigned long long below = (1ull << lane) - 1ull;
+  const int64_t base = int64_t(blockIdx.x) * RS_TILE;
+  for (int it = 0; it < RS_ITEMS; ++it) {
+#pragma unroll
+    for (int w = 0; w < RS_THREADS / 64; ++w) wcnt[w][tid] = 0u;
+    __syncthreads();
+    const int64_t idx = base + it * RS_THREADS + tid;
+    const bool valid = idx < n;
+    const unsigned long long key = valid ? kin[idx] : 0ull;
+    const int d = int((key >> shift) & 0xff);
+    // lanes of this wave holding a valid key with the same digit
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long m = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? m : ~m;
+    }
+    const unsigned rank = unsigned(__popcll(peers & below));
+    if (valid && rank == 0u) wcnt[wave][d] = unsigned(__popcll(peers));
+    __syncthreads();
+    if (valid) {
+      unsigned pos = run[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      kout[pos] = key;
+      vout[pos] = vin[idx];
+    }
+    __syncthreads();
+    unsigned add = 0u;
+#pragma unroll
+    for (int w = 0; w < RS_THREADS / 64; ++w) add += wcnt[w][tid];
+    run[tid] += add;
+  }
+}
+
+// Scratch (unsigned entries) that radix_sort needs for n pairs.
+static int64_t sort_scratch(int64_t n) {
+  const int64_t t = int64_t(RS_BINS) * nblk(n, RS_TILE);
+  return 2 * t + scan_scratch(t);
+}
+
+// Sorts (kin, vin) by the key bits [0, endbit) into (kout, vout); kin and
+// vin are overwritten (ping-pong buffers).
+static std::string radix_sort(unsigned long long* kin, int* vin, unsigned long long* kout, int* vout, int64_t n,
+                              int endbit, unsigned* scratch, hipStream_t st) {
+  if (n <= 0) return "";
+  const int tiles = nblk(n, RS_TILE);
+  const int64_t t = int64_t(RS_BINS) * tiles;
+  unsigned* table = scratch;
+  unsigned* offs = scratch + t;
+  unsigned* sscr = scratch + 2 * t;
+  const int passes = (endbit + 7) / 8;
+  unsigned long long *ka = kin, *kb = kout;
+  int *va = vin, *vb = vout;
+  for (int p = 0; p < passes; ++p) {
+    k_rs_count<<<tiles, RS_THREADS, 0, st>>>(ka, n, 8 * p, tiles, table);
+    TCHK(hipGetLastError());
+    std::string e = exclusive_sum(table, offs, t, sscr, st);
+    if (!e.empty()) return e;
+    k_rs_scatter<<<tiles, RS_THREADS, 0, st>>>(ka, va, n, 8 * p, tiles, offs, kb, vb);
+    TCHK(hipGetLastError());
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  // after an odd number of passes the result is in (kout, vout) already
+  if (ka != kout) {
+    TCHK(hipMemcpyAsync(kout, ka, n * 8, hipMemcpyDeviceToDevice, st));
+    TCHK(hipMemcpyAsync(vout, va, n * 4, hipMemcpyDeviceToDevice, st));
+  }
+  return "";
+}
+
 std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, double eta, int rule,
                         const std::vector<std::vector<int64_t>>& lo, hipStream_t st, TreeOut& out) {
   (void)leaf_max;
@@ -227,16 +408,15 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
   TCHK(hipMallocAsync(&rx, n * 4, st));
   TCHK(hipMallocAsync(&ry, n * 4, st));
   TCHK(hipMallocAsync(&perm, n * 4, st));
-  void* tmp = nullptr;
-  size_t tmpb = 0, need = 0;
-  TCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, need, kin, kout, vin, vout, (int)n, 0, 64, st));
-  tmpb = need;
-  TCHK(hipMallocAsync(&tmp, tmpb + 256, st));
+  unsigned* tmp = nullptr;
+  TCHK(hipMallocAsync(&tmp, sort_scratch(n) * 4, st));
   for (int ax = 0; ax < 2; ++ax) {
     k_axis_keys<<<nblk(n, 256), 256, 0, st>>>(loc, n, ax, kin, vin);
     TCHK(hipGetLastError());
-    size_t tb = tmpb;
-    TCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, kout, vin, vout, (int)n, 0, 64, st));
+    {
+      std::string e = radix_sort(kin, vin, kout, vout, n, 64, tmp, st);
+      if (!e.empty()) return e;
+    }
     k_scatter_rank<<<nblk(n, 256), 256, 0, st>>>(vout, n, ax == 0 ? rx : ry);
     TCHK(hipGetLastError());
   }
@@ -267,9 +447,11 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
     k_level_keys<<<nblk(n, 256), 256, 0, st>>>(perm, n, dlo, cnt, axis, rx, ry, kin, l == D ? 1 : 0);
     TCHK(hipGetLastError());
     TCHK(hipMemcpyAsync(vin, perm, n * 4, hipMemcpyDeviceToDevice, st));
-    size_t tb = tmpb;
     int endbit = 32 + (l == 0 ? 1 : l + 1);
-    TCHK(hipcub::DeviceRadixSort::SortPairs(tmp, tb, kin, kout, vin, perm, (int)n, 0, endbit, st));
+    {
+      std::string e = radix_sort(kin, vin, kout, perm, n, endbit, tmp, st);
+      if (!e.empty()) return e;
+    }
     TCHK(hipStreamSynchronize(st));
     // lo for the next level is only used by the next iteration
   }
@@ -333,27 +515,27 @@ std::string build_trees(const double* d_loc, int64_t n, int leaf_max, int D, dou
     TCHK(hipMemcpyAsync(fr, &root, 8, hipMemcpyHostToDevice, st));
   }
   int64_t cnt = 1, nleaves = 0;
-  void* stmp = nullptr;
-  size_t stmpb = 0;
+  unsigned* stmp = nullptr;
+  int64_t stmpb = 0;
   for (int l = 0; l <= D && cnt > 0; ++l) {
     std::string g = ensure_work(cnt + 1);
     if (!g.empty()) return g;
     k_classify<<<nblk(cnt, 256), 256, 0, st>>>(fr, (int)cnt, bbox_all + ((int64_t(1) << l) - 1) * 4,
                                                 eta2, rule, l == D, isl, nch, knd);
     TCHK(hipGetLastError());
-    size_t need2 = 0;
-    TCHK(hipcub::DeviceScan::ExclusiveSum(nullptr, need2, isl, lpos, (int)cnt + 1, st));
+    const int64_t need2 = scan_scratch(cnt + 1);
     if (need2 > stmpb) {
       if (stmp) TCHK(hipFreeAsync(stmp, st));
       stmpb = need2 * 2;
-      TCHK(hipMallocAsync(&stmp, stmpb, st));
+      TCHK(hipMallocAsync(&stmp, stmpb * 4, st));
     }
     TCHK(hipMemsetAsync(isl + cnt, 0, 4, st));
     TCHK(hipMemsetAsync(nch + cnt, 0, 4, st));
-    size_t tb = stmpb;
-    TCHK(hipcub::DeviceScan::ExclusiveSum(stmp, tb, isl, lpos, (int)cnt + 1, st));
-    tb = stmpb;
-    TCHK(hipcub::DeviceScan::ExclusiveSum(stmp, tb, nch, cpos, (int)cnt + 1, st));
+    {
+      std::string e = exclusive_sum((const unsigned*)isl, (unsigned*)lpos, cnt + 1, stmp, st);
+      if (e.empty()) e = exclusive_sum((const unsigned*)nch, (unsigned*)cpos, cnt + 1, stmp, st);
+      if (!e.empty()) return e;
+    }
     int tot[2];
     TCHK(hipMemcpyAsync(&tot[0], lpos + cnt, 4, hipMemcpyDeviceToHost, st));
     TCHK(hipMemcpyAsync(&tot[1], cpos + cnt, 4, hipMemcpyDeviceToHost, st));
