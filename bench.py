@@ -286,6 +286,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the planner's GEMM kernel choice (default: both GEMM kernels are timed on the "
+                         "first factorisation, outside the timed steps, and each launch keeps the faster)")
     ap.add_argument("--profile-kind", default="gemm")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch the sweep stage by stage instead of replaying captured graph segments")
@@ -331,6 +334,8 @@ def main():
     opts = {"precision": hcov.MIXED if args.precision == "mixed" else hcov.FP64}
     if args.no_graphs:
         opts["use_graphs"] = 0
+    if args.autotune:
+        opts["autotune"] = 1
     H = hcov.HCov(locs, theta0, eps=eps, leaf=leaf, eta=eta, stream=stream, opts=opts)
     t_build = time.perf_counter() - t_build
     progress(f"trees, plan and first assembly at n={n}: {t_build:.1f} s")
@@ -411,11 +416,13 @@ def main():
                       "factor_GB": st["bytes_factor"] / 1e9, "device_GB": st["bytes_device"] / 1e9,
                       "launches_per_factorisation": st["n_launches_factor"],
                       "sketch_retries": st["n_sketch_retries"],
-                      "mean_sketch_width": st["mean_sketch_width"]},
+                      "mean_sketch_width": st["mean_sketch_width"],
+                      "gemm_launches_grouped": st["n_gemm_grouped"], "autotune": bool(args.autotune),
+                      "autotune_switched": st["n_autotune_switched"]},
         # FP64 tiles of k_gemm run on the matrix cores (dense FP64 MFMA peak);
         # its products are thin (k = ranks 10-40), so their algorithmic
         # intensity sits below the ridge and HBM bandwidth is the bound
-        "roofline": {"bound": "hbm" if hbm_bound else "mfma", "kernel": f"k_{args.profile_kind}",
+        "roofline": {"bound": "hbm" if hbm_bound else "mfma", "kernel": "k_gemm + k_gemm_wide" if args.profile_kind == "gemm" else f"k_{args.profile_kind}",
                      "achieved": gbs if hbm_bound else tflops,
                      "peak": 1e3 * PEAK_HBM_TBS if hbm_bound else PEAK_FP64_TFLOPS,
                      "unit": "GB/s" if hbm_bound else "TFLOP/s",

@@ -120,6 +120,17 @@ typedef struct {
                              the weak admissibility Adm_W of Eq. (wead_adm):
                              every off-diagonal block of two different
                              clusters is low rank (eta unused) */
+  int autotune;           /* 0 (default): every GEMM launch of the sweep runs
+                             on the kernel the planner's cost model picks
+                             (one 256-thread work-group per 64x64 tile, or
+                             two lockstep groups per tile for launches bound
+                             by their longest tile); 1: the context's first
+                             factorisation is preceded by two factorisations
+                             that time every launch where both kernels are
+                             allowed, once with each, and each launch keeps
+                             the faster kernel from then on (results differ
+                             from the untuned ones by rounding only, and
+                             repeat bit for bit after the tuning) */
 } hcov_opts;
 
 #define HCOV_ADM_MIN 0
@@ -154,6 +165,10 @@ typedef struct {
   double mean_sketch_width;   /* mean sketch width of the low-rank blocks */
   int pcg_iters;              /* PCG iterations of the last quadratic form */
   double pcg_relres;          /* its final ||z - C~ x|| / ||z|| */
+  int64_t n_gemm_grouped;     /* GEMM launches of one factorisation on the
+                                 two-group kernel */
+  int64_t n_autotune_switched;/* GEMM launches the autotuning moved to the
+                                 other kernel (0 before / without it) */
 } hcov_stats_t;
 
 typedef struct hcov_ctx hcov_ctx;

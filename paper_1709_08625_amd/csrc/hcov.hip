@@ -81,6 +81,10 @@ struct hcov_ctx {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
   std::vector<Stage> prof_stages;
   std::vector<double> prof_times;   // per-launch ms of the last profiling session
+  std::vector<std::pair<int, int>> prof_where;   // (sweep step, stage) of each profiled launch, step -1 outside
+  int prof_step = -1;                            // sweep step being launched
+  bool tuned = false;                            // the GEMM kernel choice was timed (opts.autotune)
+  int64_t n_switched = 0;                        // GEMM launches the tuning moved to the other kernel
   // state
   bool assembled = false, factored = false;
   double ms_tree = 0, ms_asm = 0, ms_fact = 0, ms_solve = 0;
@@ -216,6 +220,7 @@ int run_stages(hcov_ctx* c, const std::vector<Stage>& st, const LaunchCtx* Lx = 
       HIPCHK(c, hipEventRecord(b, sm));
       c->prof_ev.emplace_back(a, b);
       c->prof_stages.push_back(s);
+      c->prof_where.emplace_back(c->prof_step, int(&s - st.data()));
     } else {
       HIPCHK(c, launch_stage(s, LC, sm));
     }
@@ -443,8 +448,10 @@ int factor(hcov_ctx* c, const double* z_dev_cluster, bool fuse) {
     HIPCHK(c, hipEventRecord(c->ev_out, c->gstream));
     HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_out, 0));
   } else {
-    for (const auto& st : steps) {
-      r = run_stages(c, st);
+    for (size_t j = 0; j < steps.size(); ++j) {
+      c->prof_step = int(j);
+      r = run_stages(c, steps[j]);
+      c->prof_step = -1;
       if (r) return r;
     }
   }
@@ -462,7 +469,107 @@ int to_cluster(hcov_ctx* c, const double* z, int where, double* dst);
 // fused into the sweep.  A saturated sketch re-assembles C~ and factorises
 // again with the saturated blocks' sketches widened (at most
 // MAX_SKETCH_RETRIES times).
+int factorise_once(hcov_ctx* c, const double* z, int where);
+
+// Launches of one stage kind (ST_GEMM: both GEMM kernels) are bracketed by
+// events from here on.
+int profile_begin(hcov_ctx* c, int kind) {
+  c->prof_kind = kind;
+  c->prof_ev.clear();
+  c->prof_stages.clear();
+  c->prof_where.clear();
+  return HCOV_OK;
+}
+
+// Waits for the profiled launches and turns their events into prof_times
+// (ms, launch order; prof_where says where each was launched); summed ms,
+// algorithmic flops and bytes to the optional outputs.
+int profile_collect(hcov_ctx* c, double* ms_out, double* fl_out, double* by_out) {
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream2));
+  std::vector<int> dyn(c->plan.n_dyn + 1);
+  HIPCHK(c, hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double ms = 0.0, fl = 0.0, by = 0.0;
+  c->prof_times.clear();
+  int rc = HCOV_OK;
+  for (size_t i = 0; i < c->prof_ev.size(); ++i) {
+    float t = 0.f;
+    if (rc == HCOV_OK && hipEventElapsedTime(&t, c->prof_ev[i].first, c->prof_ev[i].second) != hipSuccess)
+      rc = fail(c, HCOV_EDEVICE, "event timing failed");
+    ms += t;
+    c->prof_times.push_back(t);
+    double f1 = 0.0, b1 = 0.0;
+    stage_work(c->plan, dyn, c->prof_stages[i], &f1, &b1);
+    fl += f1;
+    by += b1;
+    (void)hipEventDestroy(c->prof_ev[i].first);
+    (void)hipEventDestroy(c->prof_ev[i].second);
+  }
+  c->prof_ev.clear();
+  c->prof_stages.clear();
+  if (ms_out) *ms_out = ms;
+  if (fl_out) *fl_out = fl;
+  if (by_out) *by_out = by;
+  return rc;
+}
+
+// opts.autotune: the two GEMM kernels are timed on every sweep launch that
+// both may run (two factorisations with events around the GEMM launches,
+// the second with those launches switched to the other kernel), and each
+// launch keeps the faster one.  Saturation retries inside the timed
+// factorisations only add samples (the minimum per launch counts).
+int autotune(hcov_ctx* c, const double* z, int where) {
+  auto& steps = c->plan.steps;
+  auto is_gemm = [](const Stage& s) { return s.kind == ST_GEMM || s.kind == ST_GEMM_WIDE; };
+  std::vector<std::vector<double>> best[2];
+  for (int pass = 0; pass < 2; ++pass) {
+    best[pass].assign(steps.size(), {});
+    for (size_t j = 0; j < steps.size(); ++j) best[pass][j].assign(steps[j].size(), 1e300);
+    if (pass == 1)
+      for (auto& st : steps)
+        for (auto& s : st)
+          if (is_gemm(s) && s.alt) s.kind = s.kind == ST_GEMM ? ST_GEMM_WIDE : ST_GEMM;
+    int r = profile_begin(c, ST_GEMM);
+    if (r) return r;
+    r = factorise_once(c, z, where);
+    int r2 = profile_collect(c, nullptr, nullptr, nullptr);
+    c->prof_kind = -1;
+    if (r) return r;
+    if (r2) return r2;
+    for (size_t i = 0; i < c->prof_where.size(); ++i) {
+      const auto& w = c->prof_where[i];
+      if (w.first < 0) continue;
+      double& b = best[pass][size_t(w.first)][size_t(w.second)];
+      b = std::min(b, c->prof_times[i]);
+    }
+  }
+  // the stages are in their pass-1 (switched) state: switch back where the
+  // planner's choice was not slower
+  int64_t moved = 0;
+  for (size_t j = 0; j < steps.size(); ++j)
+    for (size_t i = 0; i < steps[j].size(); ++i) {
+      Stage& s = steps[j][i];
+      if (!is_gemm(s) || !s.alt) continue;
+      if (best[0][j][i] <= best[1][j][i])
+        s.kind = s.kind == ST_GEMM ? ST_GEMM_WIDE : ST_GEMM;
+      else
+        ++moved;
+    }
+  c->n_switched = moved;
+  c->tuned = true;
+  return HCOV_OK;
+}
+
 int factorise(hcov_ctx* c, const double* z, int where) {
+  if (c->opts.autotune && !c->tuned) {
+    int r = autotune(c, z, where);
+    if (r) return r;
+  }
+  return factorise_once(c, z, where);
+}
+
+int factorise_once(hcov_ctx* c, const double* z, int where) {
   for (int attempt = 0;; ++attempt) {
     int r;
     if (!c->assembled) {
@@ -558,6 +665,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   if (!(o.pcg_tol > 0 && o.pcg_tol < 1) || o.pcg_max_iter < 1) return HCOV_EINVAL;
   if (o.fixed_rank < 0 || o.fixed_rank > o.max_rank) return HCOV_EINVAL;
   if (o.adm_rule != HCOV_ADM_MIN && o.adm_rule != HCOV_ADM_MAX && o.adm_rule != HCOV_ADM_WEAK) return HCOV_EINVAL;
+  if (o.autotune != 0 && o.autotune != 1) return HCOV_EINVAL;
   std::vector<double> h(2 * n);
   for (int64_t i = 0; i < 2 * n; ++i) {
     if (!std::isfinite(locs[i])) return HCOV_EINVAL;
@@ -1168,6 +1276,10 @@ int hcov_stats(const hcov_ctx* c, hcov_stats_t* s) {
   s->sketch_saturated = c->sat_last;
   s->pcg_iters = c->pcg_iters;
   s->pcg_relres = c->pcg_relres;
+  s->n_autotune_switched = c->n_switched;
+  s->n_gemm_grouped = 0;
+  for (const auto& st : P.steps)
+    for (const auto& x : st) s->n_gemm_grouped += x.kind == ST_GEMM_WIDE ? 1 : 0;
   // ranks
   std::vector<int> dyn(P.n_dyn + 1);
   if (hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
@@ -1265,40 +1377,16 @@ int hcov_profile_begin(hcov_ctx* c, int stage_kind) {
   if (!c || stage_kind < 0 || stage_kind > ST_TRMM || stage_kind == ST_COPY_RANK || stage_kind == ST_FORK ||
       stage_kind == ST_JOIN)
     return HCOV_EINVAL;
-  c->prof_kind = stage_kind;
-  c->prof_ev.clear();
-  c->prof_stages.clear();
-  return HCOV_OK;
+  return profile_begin(c, stage_kind);
 }
 
 int hcov_profile_end(hcov_ctx* c, int64_t* launches, double* total_ms, double* flops, double* bytes) {
   if (!c) return HCOV_EINVAL;
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  std::vector<int> dyn(c->plan.n_dyn + 1);
-  HIPCHK(c, hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  double ms = 0.0, fl = 0.0, by = 0.0;
-  c->prof_times.clear();
-  for (size_t i = 0; i < c->prof_ev.size(); ++i) {
-    float t = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&t, c->prof_ev[i].first, c->prof_ev[i].second));
-    ms += t;
-    c->prof_times.push_back(t);
-    double f1 = 0.0, b1 = 0.0;
-    stage_work(c->plan, dyn, c->prof_stages[i], &f1, &b1);
-    fl += f1;
-    by += b1;
-    (void)hipEventDestroy(c->prof_ev[i].first);
-    (void)hipEventDestroy(c->prof_ev[i].second);
-  }
-  if (launches) *launches = int64_t(c->prof_ev.size());
-  if (total_ms) *total_ms = ms;
-  if (flops) *flops = fl;
-  if (bytes) *bytes = by;
+  const int64_t nl = int64_t(c->prof_ev.size());
+  const int rc = profile_collect(c, total_ms, flops, bytes);
+  if (launches) *launches = nl;
   c->prof_kind = -1;
-  c->prof_ev.clear();
-  c->prof_stages.clear();
-  return HCOV_OK;
+  return rc;
 }
 
 int hcov_profile_times(const hcov_ctx* c, double* times_ms, int64_t max_n, int64_t* n_out) {

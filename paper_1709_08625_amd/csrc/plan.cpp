@@ -232,7 +232,7 @@ class Builder {
       }
       const int64_t plain = std::max<int64_t>(cmax, (plain_tot + 1023) / 1024);
       const int64_t wide = std::max<int64_t>((cmax + GEMM_GROUPS - 1) / GEMM_GROUPS, (wide_tot + 255) / 256);
-      out.push_back(Stage{wide_ok && wide < plain ? ST_GEMM_WIDE : ST_GEMM, t0, t1, cur_lane});
+      out.push_back(Stage{wide_ok && wide < plain ? ST_GEMM_WIDE : ST_GEMM, t0, t1, cur_lane, wide_ok ? 1 : 0});
     }
   }
 

@@ -150,6 +150,7 @@ struct Stage {
   int32_t kind;
   int32_t begin, end;   // item range in the kind's array (tiles for GEMM)
   int32_t lane = 0;     // 0: the context's stream, 1: its second stream
+  int32_t alt = 0;      // GEMM: 1 when the other GEMM kernel may run it too
 };
 
 // ---------------------------------------------------------------- tree data

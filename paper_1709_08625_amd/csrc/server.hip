@@ -129,6 +129,7 @@ struct hcov_server {
         o.free = async_free;
         o.alloc_user = (void*)st;
         o.use_graphs = 0;   // a one-shot context would not replay a captured sweep
+        o.autotune = 0;     // nor profit from timing its GEMM launches
         hcov_ctx* c = nullptr;
         int rc = hcov_build(r.locs.data(), r.n, r.theta, r.eps, r.leaf, r.eta, &o, (void*)st, &c);
         if (rc == HCOV_OK || rc == HCOV_ERANK) {

@@ -45,7 +45,7 @@ class Opts(C.Structure):
                 ("free", FREE_FN), ("alloc_user", C.c_void_p), ("use_graphs", C.c_int),
                 ("oversample", C.c_int), ("on_saturation", C.c_int), ("keep_matrix", C.c_int),
                 ("quad_mode", C.c_int), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int), ("fixed_rank", C.c_int),
-                ("adm_rule", C.c_int)]
+                ("adm_rule", C.c_int), ("autotune", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -56,7 +56,8 @@ class Stats(C.Structure):
                 ("ms_factor", C.c_double), ("ms_solve", C.c_double), ("n_steps", C.c_int64),
                 ("n_launches_factor", C.c_int64), ("n_graph_replays", C.c_int64),
                 ("n_sketch_retries", C.c_int64), ("sketch_saturated", C.c_int), ("mean_sketch_width", C.c_double),
-                ("pcg_iters", C.c_int), ("pcg_relres", C.c_double)]
+                ("pcg_iters", C.c_int), ("pcg_relres", C.c_double), ("n_gemm_grouped", C.c_int64),
+                ("n_autotune_switched", C.c_int64)]
 
 
 _lib = None
