@@ -233,9 +233,9 @@ def large2m(args, hcov, workloads):
     """The large instance: n = 2,000,000 locations (70% uniform in [0,1]^2,
     30% from 20 Gaussian clusters of sd 0.01), sigma2 1, ell 0.1, nu 0.5,
     nugget 1e-4, eps 1e-6, leaf 128, eta 2; z = L~ xi drawn at the truth;
-    the library's Nelder-Mead over (sigma2, ell, nu) from truth x (1.2, 0.8,
-    1.1), run as restarted searches of --round evaluations each (a progress
-    line per search) for --evals evaluations in all."""
+    the library's Nelder-Mead (hcov_nm_minimize, the initial steps of
+    hcov_fit) over (sigma2, ell, nu) from truth x (1.2, 0.8, 1.1) for --evals
+    evaluations, each re-assembling and factorising C~ for its theta."""
     n, truth, nug, leaf, eta, eps = args.n if args.n != 512000 else 2000000, (1.0, 0.1, 0.5), 1e-4, 128, 2.0, 1e-6
     locs, xi = workloads.mixture(n, seed=0)
     opts = {"precision": hcov.MIXED if args.precision == "mixed" else hcov.FP64}
@@ -248,17 +248,30 @@ def large2m(args, hcov, workloads):
     z = H.sample(xi[H.perm()])
     t_draw = time.perf_counter() - t1
     progress(f"z = L~xi drawn in {t_draw:.1f} s")
-    theta = np.array(truth) * np.array([1.2, 0.8, 1.1])
-    done, t_fit, hist_all = 0, 0.0, []
-    while done < args.evals:
-        k = min(args.round, args.evals - done)
-        t2 = time.perf_counter()
-        th, ll, ne, hist = H.fit(z, theta, nug, max_evals=k)
-        t_fit += time.perf_counter() - t2
-        done += ne
-        hist_all += [(list(map(float, h[0])), float(h[1])) for h in hist]
-        theta = np.asarray(th, dtype=np.float64)
-        progress(f"{done} evaluations: sigma2 {th[0]:.4f} ell {th[1]:.4f} nu {th[2]:.4f} loglik {ll:.6e}")
+    theta0 = np.array(truth) * np.array([1.2, 0.8, 1.1])
+    hist_all = []
+    t2 = time.perf_counter()
+
+    def negll(x):
+        # -L~ of Eq. (1) at theta = x (outside the domain or not positive
+        # definite: +inf, as in hcov_fit); one progress line per evaluation
+        if min(x) <= 0.0:
+            v = float("inf")
+        else:
+            try:
+                H.set_theta((float(x[0]), float(x[1]), float(x[2]), nug))
+                v = -H.loglik(z)[0]
+            except hcov.HcovError:
+                v = float("inf")
+        hist_all.append(([float(a) for a in x], v))
+        progress(f"evaluation {len(hist_all)}: theta ({x[0]:.4f}, {x[1]:.4f}, {x[2]:.4f}) -loglik {v:.6e} "
+                 f"({time.perf_counter() - t2:.0f} s)")
+        return v
+
+    th, fbest, done = hcov.nm_minimize(negll, theta0, np.array([0.01, 0.04, 0.02]), max_evals=args.evals,
+                                       size_tol=1e-5)[:3]
+    t_fit = time.perf_counter() - t2
+    theta = np.asarray(th, dtype=np.float64)
     st = H.stats()
     H.close()
     return {
@@ -269,10 +282,10 @@ def large2m(args, hcov, workloads):
         "data": "synthetic",
         "config": {"workload": f"n {n}: 70% uniform [0,1]^2 + 30% from 20 Gaussian clusters (sd 0.01), sigma2 1, "
                                f"ell 0.1, nu 0.5, nugget 1e-4, eps {eps}, leaf {leaf}, eta {eta}, z = L~xi at the "
-                               f"truth, Nelder-Mead from truth x (1.2, 0.8, 1.1) restarted every {args.round} "
-                               f"evaluations", "precision": args.precision},
+                               f"truth, Nelder-Mead from truth x (1.2, 0.8, 1.1), {args.evals} evaluations",
+                   "precision": args.precision},
         "build_s": t_build, "draw_s": t_draw, "fit_s": t_fit, "evaluations": done,
-        "theta_hat": [float(x) for x in theta], "history": hist_all,
+        "theta_hat": [float(x) for x in theta], "loglik_hat": -float(fbest), "history": hist_all,
         "structure": {"device_GB": st["bytes_device"] / 1e9, "factor_GB": st["bytes_factor"] / 1e9,
                       "max_rank": st["max_rank_seen"], "mean_rank": st["mean_rank"],
                       "lr_blocks": st["n_lr_blocks"], "dense_blocks": st["n_dense_blocks"]},
@@ -299,7 +312,6 @@ def main():
     ap.add_argument("--evals", type=int, default=30)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--requests", type=int, default=96)
-    ap.add_argument("--round", type=int, default=4, help="large2m: evaluations per restarted search")
     ap.add_argument("--slots", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
