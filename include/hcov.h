@@ -131,6 +131,12 @@ typedef struct {
                              the faster kernel from then on (results differ
                              from the untuned ones by rounding only, and
                              repeat bit for bit after the tuning) */
+  uint64_t seed;          /* seed of the Gaussian test matrix of the
+                             randomised sketches (0, the default: the
+                             library's fixed seed); other seeds give other
+                             sketches and results that differ within the
+                             truncation accuracy.  Every evaluation of a
+                             context uses the same matrix. */
 } hcov_opts;
 
 #define HCOV_ADM_MIN 0

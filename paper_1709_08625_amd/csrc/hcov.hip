@@ -804,7 +804,8 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   if (!c->d_dyn || !c->d_status || !c->d_logdet || !c->d_part || !c->d_tmp) return bail(HCOV_ENOMEM);
   hipMemsetAsync(c->d_dyn, 0, (P.n_dyn + 1) * 4, c->stream);
   // fixed Gaussian test matrix of the randomised range finder
-  if (launch_gaussian(c->d_buf[B_OMEGA], P.omega_rows * P.rcap, 0x5eed5eedULL, c->stream) != hipSuccess)
+  if (launch_gaussian(c->d_buf[B_OMEGA], P.omega_rows * P.rcap, o.seed ? o.seed : 0x5eed5eedULL, c->stream) !=
+      hipSuccess)
     return bail(HCOV_EDEVICE);
   // job arrays
   std::vector<FillJob> fj;
@@ -1318,9 +1319,10 @@ int hcov_estimate_bytes(const double* locs, int64_t n, double eps, int leaf, dou
   hcov_opts_default(&o);
   if (opts) o = *opts;
   // upper bound from sizes alone: dense leaves near the diagonal scale with n,
-  // low-rank storage with n log n.  Computed exactly by building the trees on
-  // the host would need the reference code; here a conservative bound is used
-  // by the serving admission (documented in the header).
+  // low-rank storage with n log n.  The exact figure needs the trees and the
+  // plan (built on the device and the host at hcov_build); the serving
+  // admission runs at submission, before either exists, so it takes this
+  // conservative bound (documented in the header).
   int D = tree_depth(n, leaf);
   double L = double(leaf);
   double dense = 16.0 * double(n) * L;                   // ~C_sp leaves per row

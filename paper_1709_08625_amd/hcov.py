@@ -45,7 +45,7 @@ class Opts(C.Structure):
                 ("free", FREE_FN), ("alloc_user", C.c_void_p), ("use_graphs", C.c_int),
                 ("oversample", C.c_int), ("on_saturation", C.c_int), ("keep_matrix", C.c_int),
                 ("quad_mode", C.c_int), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int), ("fixed_rank", C.c_int),
-                ("adm_rule", C.c_int), ("autotune", C.c_int)]
+                ("adm_rule", C.c_int), ("autotune", C.c_int), ("seed", C.c_uint64)]
 
 
 class Stats(C.Structure):

@@ -112,3 +112,26 @@ def test_default_oversampling_reports_saturation_state():
     print(f"  nearby theta: retries {st2['n_sketch_retries'] - st['n_sketch_retries']}")
     assert st2["sketch_saturated"] == 0
     h.close()
+
+
+def test_sketch_seed():
+    # opts.seed draws another Gaussian test matrix: the sketches differ, the
+    # likelihood stays within the FP64 tolerance of the dense oracle, and one
+    # seed repeats bit for bit
+    hcov = _hc()
+    n, th = 3000, (1.0, 0.08, 0.8, 1e-4)
+    locs, xi = workloads.uniform(n, seed=31)
+    z = dense.sample_field(locs, xi, *th)
+    ll0, ld0, q0 = dense.loglik_parts(locs, z, *th)
+    S = scale(n, ld0, q0)
+    res = {}
+    for seed in (0, 12345, 12345):
+        h = hcov.HCov(locs, th, eps=1e-8, leaf=64, eta=2.0, opts={"seed": seed})
+        try:
+            r = h.loglik(z)
+        finally:
+            h.close()
+        assert abs(r[0] - ll0) / S < 1e-6
+        if seed in res:
+            assert r == res[seed]
+        res[seed] = r
