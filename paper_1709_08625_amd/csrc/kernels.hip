@@ -1108,6 +1108,9 @@ __device__ __forceinline__ void jacobi_zero_pad(double* A, double* V, int n, int
   __syncthreads();
 }
 
+// The row span G RU of a round is the smallest multiple of the group width
+// that covers n (a lane's rows of a column pair, loaded and stored per
+// round, are what a round costs).
 __device__ void jacobi_wg(double* A, double* V, int n, double thr2) {
   if (n <= 16) {
     jacobi_zero_pad(A, V, n, 16);
@@ -1115,6 +1118,12 @@ __device__ void jacobi_wg(double* A, double* V, int n, double thr2) {
   } else if (n <= 32) {
     jacobi_zero_pad(A, V, n, 32);
     jacobi_wg_rounds<16, 2>(A, V, n, thr2);
+  } else if (n <= 40) {
+    jacobi_zero_pad(A, V, n, 40);
+    jacobi_wg_rounds<8, 5>(A, V, n, thr2);
+  } else if (n <= 48) {
+    jacobi_zero_pad(A, V, n, 48);
+    jacobi_wg_rounds<8, 6>(A, V, n, thr2);
   } else {
     jacobi_zero_pad(A, V, n, 64);
     jacobi_wg_rounds<8, 8>(A, V, n, thr2);
