@@ -1732,7 +1732,13 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
       V[i * TLD + l] = (i <= l) ? R1[upk(i, l)] : 0.0;
     }
     __syncthreads();
-    if (tid < 64) qrcp_wave(V, n, eps, ord, &s_k);
+    if (tid < 64) {
+      // the register variant (a lane's column in registers) up to 40 rows
+      if (n <= 40)
+        qrcp_reg<40>(V, n, eps, ord, &s_k, sv);
+      else
+        qrcp_wave(V, n, eps, ord, &s_k);
+    }
     __syncthreads();
     const int kk = s_k;
     // X = R'_k^{-1} (R'[r][c] = V[r * TLD + ord[c]]), thread c builds column c
@@ -1788,8 +1794,13 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     // reflectors kept), one-sided Jacobi on B = R2'^T with V, then
     // Z = Q2 V[:, ord] and C1 = R2^{-1} Z_k (eight or four lanes per column).
     __shared__ int s_kk;
+    // (the row span G R of a lane group: the smallest that covers n)
     if (n <= 32)
       sketch_f_m_wg<8, 4>(R1, R2, n, A);
+    else if (n <= 40)
+      sketch_f_m_wg<4, 10>(R1, R2, n, A);
+    else if (n <= 48)
+      sketch_f_m_wg<4, 12>(R1, R2, n, A);
     else
       sketch_f_m_wg<4, 16>(R1, R2, n, A);
     // M^T = Q2 R2' by the work-group (reflectors kept), then the reflector
