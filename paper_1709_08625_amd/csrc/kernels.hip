@@ -1605,26 +1605,27 @@ __device__ void sketch_f_m_wg(const double* R1, const double* R2, int n, double*
   }
 }
 
-// C1 = Pi R'_k^{-1} for n <= 32 by the work-group: eight lanes per column
-// c < k (tid / 8), lane s holding rows s + 8 r; column c of R'_k^{-1} by
+// C1 = Pi R'_k^{-1} for n <= G R by the work-group: G lanes per column
+// c < k (tid / G), lane s holding rows s + G r; column c of R'_k^{-1} by
 // column-oriented substitution from e_c (R' read as a broadcast), each new
 // entry passed along the column's lanes by a lane permute; then row piv[u]
 // of C1 for every u < n (zero for u > c).
+template <int G, int R>
 __device__ void sketch_p_inv_wg(const double* T, const int* piv, int n, int kk, double* __restrict__ C1,
                                 int rmax) {
-  const int tid = threadIdx.x, c = tid >> 3, s = tid & 7, lane = tid & 63;
-  double x[4];
+  const int tid = threadIdx.x, c = tid / G, s = tid % G, lane = tid & 63;
+  double x[R];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) x[r] = (s + 8 * r == c) ? 1.0 : 0.0;
+  for (int r = 0; r < R; ++r) x[r] = (s + G * r == c) ? 1.0 : 0.0;
 #pragma unroll
-  for (int l = 31; l >= 0; --l) {
+  for (int l = G * R - 1; l >= 0; --l) {
     if (l < kk) {
       const int pl = piv[l];
-      double xl = x[l >> 3] / T[l * TLD + pl];   // right on the lane holding row l
-      xl = __shfl(xl, (lane & ~7) | (l & 7));
+      double xl = x[l / G] / T[l * TLD + pl];   // right on the lane holding row l
+      xl = __shfl(xl, (lane & ~(G - 1)) | (l % G));
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int u = s + 8 * r;
+      for (int r = 0; r < R; ++r) {
+        const int u = s + G * r;
         const double t = T[(u < l ? u : 0) * TLD + pl];
         x[r] = (u == l) ? xl : ((u < l) ? fma(-t, xl, x[r]) : x[r]);
       }
@@ -1632,8 +1633,8 @@ __device__ void sketch_p_inv_wg(const double* T, const int* piv, int n, int kk, 
   }
   if (c < kk) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int u = s + 8 * r;
+    for (int r = 0; r < R; ++r) {
+      const int u = s + G * r;
       if (u < n) C1[piv[u] + (size_t)c * rmax] = (u <= c) ? x[r] : 0.0;
     }
   }
@@ -1720,7 +1721,7 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     __syncthreads();
     if (tid < 64) qrcp_reg<32>(V, n, eps, ord, &s_kr, sv);
     __syncthreads();
-    sketch_p_inv_wg(V, ord, n, s_kr, C1, rmax);
+    sketch_p_inv_wg<8, 4>(V, ord, n, s_kr, C1, rmax);
     if (tid == 0) dyn[J.out_rank_slot] = s_kr;
     return;
   }
@@ -1741,23 +1742,8 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
     }
     __syncthreads();
     const int kk = s_k;
-    // X = R'_k^{-1} (R'[r][c] = V[r * TLD + ord[c]]), thread c builds column c
-    // in A (row i at A[i * TLD]) from e_c by column-oriented back substitution
-    for (int c = tid; c < kk; c += 256) {
-      for (int i = 0; i <= c; ++i) A[i * TLD + c] = (i == c) ? 1.0 : 0.0;
-      for (int l = c; l >= 0; --l) {
-        const int pl = ord[l];
-        const double xl = A[l * TLD + c] / V[l * TLD + pl];
-        A[l * TLD + c] = xl;
-        for (int i = 0; i < l; ++i) A[i * TLD + c] -= V[i * TLD + pl] * xl;
-      }
-    }
-    __syncthreads();
-    for (int e = tid; e < n * kk; e += 256) {
-      int i = e % n, c = e / n;
-      double v = (i <= c && i < kk) ? A[i * TLD + c] : 0.0;
-      C1[ord[i] + (size_t)c * rmax] = v;
-    }
+    // C1 = Pi R'_k^{-1} with four lanes per column
+    sketch_p_inv_wg<4, 16>(V, ord, n, kk, C1, rmax);
     if (tid == 0) dyn[J.out_rank_slot] = kk;
     return;
   }
