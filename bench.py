@@ -430,6 +430,8 @@ def main():
                       "sketch_retries": st["n_sketch_retries"],
                       "mean_sketch_width": st["mean_sketch_width"],
                       "gemm_launches_grouped": st["n_gemm_grouped"], "autotune": bool(args.autotune),
+                      "gemm_tflop_per_factorisation": st["gemm_flops_factor"] / 1e12,
+                      "gemm_gb_per_factorisation": st["gemm_bytes_factor"] / 1e9,
                       "autotune_switched": st["n_autotune_switched"]},
         # FP64 tiles of k_gemm run on the matrix cores (dense FP64 MFMA peak);
         # its products are thin (k = ranks 10-40), so their algorithmic

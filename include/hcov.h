@@ -175,6 +175,10 @@ typedef struct {
                                  two-group kernel */
   int64_t n_autotune_switched;/* GEMM launches the autotuning moved to the
                                  other kernel (0 before / without it) */
+  double gemm_flops_factor;   /* algorithmic GEMM flops of one factorisation
+                                 at the current ranks (2 m n k per product) */
+  double gemm_bytes_factor;   /* its algorithmic GEMM bytes (operands read
+                                 once, outputs written, accumulations read) */
 } hcov_stats_t;
 
 typedef struct hcov_ctx hcov_ctx;

@@ -1298,6 +1298,20 @@ int hcov_stats(const hcov_ctx* c, hcov_stats_t* s) {
   }
   s->max_rank_seen = int(mx);
   {
+    // planned GEMM work of one factorisation at these ranks
+    double fl = 0.0, by = 0.0;
+    for (const auto& st : P.steps)
+      for (const auto& x : st)
+        if (x.kind == ST_GEMM || x.kind == ST_GEMM_WIDE) {
+          double f1 = 0.0, b1 = 0.0;
+          stage_work(P, dyn, x, &f1, &b1);
+          fl += f1;
+          by += b1;
+        }
+    s->gemm_flops_factor = fl;
+    s->gemm_bytes_factor = by;
+  }
+  {
     // sketch width of every low-rank block in the last factorisation
     double w = 0.0;
     for (auto& B : P.blocks)

@@ -57,7 +57,8 @@ class Stats(C.Structure):
                 ("n_launches_factor", C.c_int64), ("n_graph_replays", C.c_int64),
                 ("n_sketch_retries", C.c_int64), ("sketch_saturated", C.c_int), ("mean_sketch_width", C.c_double),
                 ("pcg_iters", C.c_int), ("pcg_relres", C.c_double), ("n_gemm_grouped", C.c_int64),
-                ("n_autotune_switched", C.c_int64)]
+                ("n_autotune_switched", C.c_int64), ("gemm_flops_factor", C.c_double),
+                ("gemm_bytes_factor", C.c_double)]
 
 
 _lib = None

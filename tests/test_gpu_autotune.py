@@ -27,8 +27,14 @@ def test_autotuned_context_matches_untuned_and_oracle():
         try:
             first = H.loglik(z)
             H.set_theta(th)
+            H.profile_begin("gemm")
             again = H.loglik(z)
+            _, _, pflops, pbytes = H.profile_end()
             st = H.stats()
+            # the planned GEMM work of a factorisation in the stats is what
+            # the profiled factorisation's launches add up to
+            assert st["gemm_flops_factor"] == pytest.approx(pflops, rel=1e-12) and pflops > 0
+            assert st["gemm_bytes_factor"] == pytest.approx(pbytes, rel=1e-12)
         finally:
             H.close()
         out[tune] = (first, again, st)
