@@ -167,33 +167,50 @@ def serving(args, hcov, workloads):
 
 def fit128k(args, hcov, workloads):
     """Maximum-likelihood fit on the jittered-grid workload: n = 128,000,
-    sigma2 1, ell 0.05, nu 1.5, nugget 1e-5, leaf 64, eta 2, eps 1e-8; z drawn
-    as L~ xi from an eps = 1e-10 factorisation; Nelder-Mead from truth x
-    (1.2, 0.8, 1.1) for a fixed number of evaluations, inside the library."""
+    sigma2 1, ell 0.05, nu 1.5, nugget 1e-5, leaf 64, eta 2.  The accuracy eps
+    is the first of 1e-10, 1e-9, 1e-8 whose factorisation at the truth keeps
+    every low-rank block within the rank capacity of 64 (this smooth kernel's
+    Cholesky factor needs more at some accuracies); z = L~ xi is drawn from that
+    factorisation and Nelder-Mead runs at the same eps from truth x
+    (1.2, 0.8, 1.1) for a fixed number of evaluations, inside the library.
+    Evaluations that exceed the capacity count as +inf for the search."""
     n, truth, nug, leaf, eta = 128000, (1.0, 0.05, 1.5), 1e-5, 64, 2.0
     locs, xi = workloads.jitter_grid(n, 358, seed=0)
     t0 = time.perf_counter()
-    S = hcov.HCov(locs, (*truth, nug), eps=1e-10, leaf=leaf, eta=eta)
-    S.cholesky()
-    z = S.sample(xi[S.perm()])   # external order
-    S.close()
-    progress(f"observations drawn in {time.perf_counter() - t0:.1f} s")
+    z, eps_draw = None, None
+    for e in (1e-10, 1e-9, 1e-8):
+        S = hcov.HCov(locs, (*truth, nug), eps=e, leaf=leaf, eta=eta)
+        try:
+            S.cholesky()
+            z = S.sample(xi[S.perm()])   # external order
+            eps_draw = e
+            break
+        except hcov.HcovError as err:
+            if err.code != hcov.ERANK:
+                raise
+            progress(f"eps {e}: {err}")
+        finally:
+            S.close()
+    assert z is not None, "no drawing factorisation fits the rank capacity"
+    progress(f"observations drawn at eps {eps_draw} in {time.perf_counter() - t0:.1f} s")
     t1 = time.perf_counter()
     theta0 = np.array(truth) * np.array([1.2, 0.8, 1.1])
-    H = hcov.HCov(locs, (*theta0, nug), eps=1e-8, leaf=leaf, eta=eta)
+    H = hcov.HCov(locs, (*theta0, nug), eps=eps_draw, leaf=leaf, eta=eta)
     t_build = time.perf_counter() - t1
     t2 = time.perf_counter()
     th, ll, ne, hist = H.fit(z, theta0, nug, max_evals=args.evals)
     t_fit = time.perf_counter() - t2
     H.close()
+    failed = sum(not np.isfinite(f) for _, f in hist)
     return {
         "metric": "Nelder-Mead fit: loglik evaluations/sec inside the simplex search (n = 128k jittered grid)",
         "value": ne / t_fit, "unit": "evals/s", "n_gpus": 1, "steps": ne, "warmup": 0,
         "ms_per_step": 1e3 * t_fit / ne, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "jittered 358x358 grid, n 128000, sigma2 1, ell 0.05, nu 1.5, nugget 1e-5, leaf 64, "
-                               "eta 2, eps 1e-8, z = L~xi (eps 1e-10), start truth x (1.2, 0.8, 1.1)"},
-        "theta_hat": [float(x) for x in th], "loglik_hat": ll, "evaluations": ne, "build_s": t_build,
+                               f"eta 2, eps {eps_draw}, z = L~xi at the same eps, start truth x (1.2, 0.8, 1.1)"},
+        "theta_hat": [float(x) for x in th], "loglik_hat": ll, "evaluations": ne,
+        "failed_evaluations": failed, "build_s": t_build,
         "fit_s": t_fit,
     }
 
