@@ -319,6 +319,9 @@ def main():
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the planner's GEMM kernel choice (default: both GEMM kernels are timed on the "
                          "first factorisation, outside the timed steps, and each launch keeps the faster)")
+    ap.add_argument("--rank-cap", type=int, default=32,
+                    help="initial room of every low-rank block's U and V (0: max_rank 64 everywhere); blocks "
+                         "that need more grow, with a plan rebuild, during the first evaluations")
     ap.add_argument("--profile-kind", default="gemm")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch the sweep stage by stage instead of replaying captured graph segments")
@@ -365,6 +368,8 @@ def main():
         opts["use_graphs"] = 0
     if args.autotune:
         opts["autotune"] = 1
+    if args.rank_cap:
+        opts["initial_rank_cap"] = args.rank_cap
     H = hcov.HCov(locs, theta0, eps=eps, leaf=leaf, eta=eta, stream=stream, opts=opts)
     t_build = time.perf_counter() - t_build
     progress(f"trees, plan and first assembly at n={n}: {t_build:.1f} s")
@@ -387,6 +392,7 @@ def main():
     torch.cuda.synchronize()
     lat = []
     lls = []
+    replans0 = H.stats()["n_replans"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -449,7 +455,9 @@ def main():
                       "gemm_launches_grouped": st["n_gemm_grouped"], "autotune": bool(args.autotune),
                       "gemm_tflop_per_factorisation": st["gemm_flops_factor"] / 1e12,
                       "gemm_gb_per_factorisation": st["gemm_bytes_factor"] / 1e9,
-                      "autotune_switched": st["n_autotune_switched"]},
+                      "autotune_switched": st["n_autotune_switched"],
+                      "initial_rank_cap": args.rank_cap, "lowrank_GB": st["bytes_lowrank"] / 1e9,
+                      "replans": st["n_replans"], "replans_timed": st["n_replans"] - replans0},
         # FP64 tiles of k_gemm run on the matrix cores (dense FP64 MFMA peak);
         # its products are thin (k = ranks 10-40), so their algorithmic
         # intensity sits below the ridge and HBM bandwidth is the bound

@@ -137,6 +137,19 @@ typedef struct {
                              sketches and results that differ within the
                              truncation accuracy.  Every evaluation of a
                              context uses the same matrix. */
+  int initial_rank_cap;   /* 0 (default): every low-rank block's U and V
+                             arenas hold max_rank columns.  k in [1, max_rank]:
+                             each block starts with room for k columns and is
+                             grown (to at least twice its room and 5/4 of the
+                             rank asked for, at most max_rank) when the ACA or
+                             a truncation of the factorisation needs more; a
+                             growth rebuilds the plan and the device buffers
+                             and repeats the assembly and factorisation that
+                             hit it, inside the same call (the results equal
+                             those at full room up to rounding).  Capacities
+                             only grow, over the life of the context.
+                             HCOV_ERANK still means a block needs more than
+                             max_rank.  Ignored with fixed_rank > 0. */
 } hcov_opts;
 
 #define HCOV_ADM_MIN 0
@@ -179,6 +192,10 @@ typedef struct {
                                  at the current ranks (2 m n k per product) */
   double gemm_bytes_factor;   /* its algorithmic GEMM bytes (operands read
                                  once, outputs written, accumulations read) */
+  int64_t n_replans;          /* plan rebuilds that grew block capacities
+                                 (opts.initial_rank_cap) */
+  int64_t bytes_lowrank;      /* bytes of the U and V arenas of the low-rank
+                                 blocks at their current capacities */
 } hcov_stats_t;
 
 typedef struct hcov_ctx hcov_ctx;

@@ -288,9 +288,12 @@ __global__ void k_acab_update(double* __restrict__ Vb, const AcaJob* __restrict_
     S.k = k + 1;
     S.pending = 1;
     bool stop = sqrt(nuv) <= eps_aca * sqrt(fmax(S.nrm2, 0.0));
-    const int kmax = min(min(J.p, J.q), kcap);
+    const int kmax = min(min(J.p, J.q), min(kcap, J.cap));
     if (S.k >= kmax) {
-      if (!stop && kmax < min(J.p, J.q) && !cap_ok) atomicOr(status, STAT_RANK_OVERFLOW);
+      if (!stop && kmax < min(J.p, J.q) && !cap_ok) {
+        atomicOr(status, STAT_RANK_OVERFLOW);
+        if (J.need_slot >= 0) atomicMax(dyn + J.need_slot, kmax + 1);
+      }
       stop = true;
     }
     if (!stop) {

@@ -34,7 +34,14 @@ struct hcov_ctx {
   std::vector<int64_t> blocks_lac;
   // device memory
   std::vector<void*> allocs;
+  std::vector<size_t> alloc_bytes;
+  size_t n_base_allocs = 0;   // allocations that do not depend on the plan (locations, permutation)
   int64_t bytes = 0;
+  // per-block rank capacities (opts.initial_rank_cap; empty: max_rank everywhere)
+  bool sizing = false;
+  std::vector<int32_t> caps;
+  int64_t n_replans = 0;
+  bool plan_ok = false;       // plan-dependent buffers exist (false after a failed rebuild)
   double* d_loc = nullptr;     // double2[n], cluster order
   int* d_perm = nullptr;       // int32[n]
   double* d_buf[B_COUNT] = {};
@@ -118,6 +125,7 @@ void* dev_alloc(hcov_ctx* c, size_t bytes) {
   }
   if (p) {
     c->allocs.push_back(p);
+    c->alloc_bytes.push_back(bytes);
     c->bytes += int64_t(bytes);
   }
   return p;
@@ -296,12 +304,64 @@ void stage_work(const Plan& P, const std::vector<int>& dyn, const Stage& s, doub
 constexpr int SAT_RETRY = 1;
 constexpr double MIXED_EPS_FLOOR = 1e-6;
 constexpr int MAX_SKETCH_RETRIES = 4;
+// Internal (positive) result of an assembly or factorisation in which a
+// block asked for more rank than its arena holds, below max_rank: the
+// capacities were grown and the plan must be rebuilt before a repeat.
+constexpr int GROW_REPLAN = 2;
+constexpr int MAX_REPLANS = 8;
+
+int setup_plan(hcov_ctx* c);
+int replan(hcov_ctx* c);
+
+// Raises the capacity of every low-rank block whose ACA or truncation asked
+// for more than it holds (dyn need slots): to at least twice the old
+// capacity and 3/2 of the request, rounded up to 8, at most max_rank.  The
+// same rebuild gives blocks whose kept rank fills 3/4 of their room or more
+// room for 3/2 of it, so that the next parameters rarely force another.
+// Returns the number of overflowing blocks grown (0: none could grow, no
+// rebuild is due), or an error.
+int grow_caps(hcov_ctx* c) {
+  const Plan& P = c->plan;
+  std::vector<int> dyn(P.n_dyn + 1);
+  HIPCHK(c, hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const int kcap = P.kcap;
+  int grown = 0;
+  auto up8 = [](int x) { return (x + 7) / 8 * 8; };
+  std::vector<int32_t> next(c->caps);
+  for (size_t b = 0; b < P.blocks.size(); ++b) {
+    const BlockInfo& B = P.blocks[b];
+    if (B.kind != 1 || B.cap >= kcap) continue;
+    const int need = dyn[B.need_slot], kept = dyn[B.rank_slot];
+    int want = B.cap;
+    if (need > B.cap) {
+      want = std::max(2 * B.cap, up8(need + need / 2));
+      ++grown;
+    } else if (4 * kept >= 3 * B.cap) {
+      want = up8(kept + kept / 2);
+    }
+    next[b] = int32_t(std::min(kcap, std::max(B.cap, want)));
+  }
+  if (grown) c->caps.swap(next);
+  return grown;
+}
 
 int check_status(hcov_ctx* c, bool spd_matters) {
   int st[3];
   HIPCHK(c, hipMemcpyAsync(st, c->d_status, 12, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (spd_matters) c->sat_last = st[2];
+  if (c->sizing && (st[0] & STAT_RANK_OVERFLOW)) {
+    const int g = grow_caps(c);
+    if (g < 0) return g;
+    if (g > 0) {
+      c->factored = false;
+      // widened sketch hints of this factorisation carry over to the rebuilt plan
+      if (spd_matters && (st[0] & STAT_SKETCH_SAT) && !(st[0] & STAT_SAT_CAP))
+        HIPCHK(c, launch_adopt_hints(c->L, c->stream));
+      return GROW_REPLAN;
+    }
+  }
   if (spd_matters && (st[0] & STAT_SKETCH_SAT)) {
     // a saturated sketch may also have spoiled a later pivot: the retry (or
     // the error) comes first
@@ -334,6 +394,7 @@ double now_ms() {
 }
 
 int assemble(hcov_ctx* c) {
+  if (!c->plan_ok) return fail(c, HCOV_ESTATE, "the plan rebuild of a capacity growth failed; context unusable");
   double t0 = now_ms();
   c->mp = make_params(c->theta);
   int r = reset_status(c);
@@ -431,6 +492,7 @@ void capture_sweep(hcov_ctx* c, const std::vector<std::vector<Stage>>& steps) {
 }
 
 int factor(hcov_ctx* c, const double* z_dev_cluster, bool fuse) {
+  if (!c->plan_ok) return fail(c, HCOV_ESTATE, "the plan rebuild of a capacity growth failed; context unusable");
   if (!c->assembled) return fail(c, HCOV_ESTATE, "matrix not assembled");
   double t0 = now_ms();
   int r = reset_status(c);
@@ -519,7 +581,8 @@ int profile_collect(hcov_ctx* c, double* ms_out, double* fl_out, double* by_out)
 // the second with those launches switched to the other kernel), and each
 // launch keeps the faster one.  Saturation retries inside the timed
 // factorisations only add samples (the minimum per launch counts).
-int autotune(hcov_ctx* c, const double* z, int where) {
+int autotune_once(hcov_ctx* c, const double* z, int where) {
+  const int64_t rp0 = c->n_replans;
   auto& steps = c->plan.steps;
   auto is_gemm = [](const Stage& s) { return s.kind == ST_GEMM || s.kind == ST_GEMM_WIDE; };
   std::vector<std::vector<double>> best[2];
@@ -537,6 +600,9 @@ int autotune(hcov_ctx* c, const double* z, int where) {
     c->prof_kind = -1;
     if (r) return r;
     if (r2) return r2;
+    // a capacity growth rebuilt the plan (its stages are the planner's
+    // again): the caller starts the tuning over
+    if (c->n_replans != rp0) return HCOV_OK;
     for (size_t i = 0; i < c->prof_where.size(); ++i) {
       const auto& w = c->prof_where[i];
       if (w.first < 0) continue;
@@ -561,6 +627,14 @@ int autotune(hcov_ctx* c, const double* z, int where) {
   return HCOV_OK;
 }
 
+int autotune(hcov_ctx* c, const double* z, int where) {
+  for (int round = 0; round <= MAX_REPLANS && !c->tuned; ++round) {
+    const int r = autotune_once(c, z, where);
+    if (r) return r;
+  }
+  return HCOV_OK;
+}
+
 int factorise(hcov_ctx* c, const double* z, int where) {
   if (c->opts.autotune && !c->tuned) {
     int r = autotune(c, z, where);
@@ -570,10 +644,22 @@ int factorise(hcov_ctx* c, const double* z, int where) {
 }
 
 int factorise_once(hcov_ctx* c, const double* z, int where) {
-  for (int attempt = 0;; ++attempt) {
+  int attempt = 0, grows = 0;
+  auto grow = [&]() -> int {
+    if (++grows > MAX_REPLANS)
+      return fail(c, HCOV_ERANK, "block rank capacities still growing after " + std::to_string(MAX_REPLANS) +
+                                     " plan rebuilds");
+    return replan(c);
+  };
+  for (;;) {
     int r;
     if (!c->assembled) {
       r = assemble(c);
+      if (r == GROW_REPLAN) {
+        r = grow();
+        if (r) return r;
+        continue;
+      }
       if (r) return r;
     }
     if (z) {
@@ -581,10 +667,16 @@ int factorise_once(hcov_ctx* c, const double* z, int where) {
       if (r) return r;
     }
     r = factor(c, nullptr, z != nullptr);
+    if (r == GROW_REPLAN) {
+      r = grow();
+      if (r) return r;
+      continue;
+    }
     if (r != SAT_RETRY) return r;
     if (attempt >= MAX_SKETCH_RETRIES)
       return fail(c, HCOV_ERANK, "sketches still saturated after " + std::to_string(MAX_SKETCH_RETRIES) +
                                      " retries with doubled widths");
+    ++attempt;
     c->n_retries += 1;
   }
 }
@@ -617,6 +709,250 @@ int logdet_sum(hcov_ctx* c, double* out) {
   if (r) return r;
   *out = 2.0 * s;
   return HCOV_OK;
+}
+
+// Plan, device buffers, job arrays and launch contexts of the current block
+// capacities (c->caps; empty: every block at max_rank).  Everything
+// allocated here comes after the first n_base_allocs allocations of the
+// context, so that release_plan can give it back before a rebuild.
+int setup_plan(hcov_ctx* c) {
+  const int64_t n = c->n;
+  const hcov_opts& o = c->opts;
+  // plan
+  int64_t nb = int64_t(c->blocks_lac.size() / 4);
+  std::string e = build_plan(c->plan, n, c->D, c->leaf, c->blocks_lac.data(), nb, o.max_rank,
+                             o.precision == HCOV_MIXED, c->caps.empty() ? nullptr : c->caps.data());
+  if (!e.empty()) {
+    c->err = e;
+    return HCOV_EINVAL;
+  }
+  Plan& P = c->plan;
+  // memory estimate check
+  size_t need = size_t(P.dense_elems + P.u_elems + P.v_elems + P.scr_elems + P.pers_elems + P.omega_rows * P.rcap +
+                       2 * P.rhs_ld + P.linv_elems) * 8;
+  if (c->keep) need += size_t(P.dense_elems + P.u_elems + P.v_elems + 6 * n) * 8;
+  if (o.mem_cap_bytes && need > o.mem_cap_bytes) {
+    c->err = "estimate " + std::to_string(need) + " bytes exceeds the memory cap";
+    return HCOV_ENOMEM;
+  }
+  c->d_buf[B_DENSE] = (double*)dev_alloc(c, P.dense_elems * 8);
+  c->d_buf[B_U] = (double*)dev_alloc(c, P.u_elems * 8);
+  c->d_buf[B_V] = (double*)dev_alloc(c, P.v_elems * 8);
+  c->d_buf[B_SCR] = (double*)dev_alloc(c, P.scr_elems * 8);
+  c->d_buf[B_OMEGA] = (double*)dev_alloc(c, P.omega_rows * P.rcap * 8);
+  c->d_buf[B_RHS] = (double*)dev_alloc(c, 2 * P.rhs_ld * 8);
+  c->d_buf[B_PERS] = (double*)dev_alloc(c, P.pers_elems * 8);
+  c->d_buf[B_LINV] = (double*)dev_alloc(c, P.linv_elems * 8);
+  c->d_dyn = (int*)dev_alloc(c, (P.n_dyn + 1) * 4);
+  c->d_status = (int*)dev_alloc(c, 16);
+  int64_t m = int64_t(1) << c->D;
+  c->d_logdet = (double*)dev_alloc(c, m * 8);
+  c->d_part = (double*)dev_alloc(c, ((n + 1023) / 1024 + m / 1024 + 8) * 8);
+  c->d_tmp = (double*)dev_alloc(c, n * 8);
+  for (int b = 0; b < B_COUNT; ++b)
+    if (!c->d_buf[b]) return HCOV_ENOMEM;
+  if (c->keep) {
+    c->d_keep[0] = (double*)dev_alloc(c, P.dense_elems * 8);
+    c->d_keep[1] = (double*)dev_alloc(c, P.u_elems * 8);
+    c->d_keep[2] = (double*)dev_alloc(c, P.v_elems * 8);
+    c->d_dyn_keep = (int*)dev_alloc(c, (P.n_dyn + 1) * 4);
+    c->d_vec = (double*)dev_alloc(c, 6 * n * 8);
+    if (!c->d_keep[0] || !c->d_keep[1] || !c->d_keep[2] || !c->d_dyn_keep || !c->d_vec) return HCOV_ENOMEM;
+  }
+  if (!c->d_dyn || !c->d_status || !c->d_logdet || !c->d_part || !c->d_tmp) return HCOV_ENOMEM;
+  if (hipMemsetAsync(c->d_dyn, 0, (P.n_dyn + 1) * 4, c->stream) != hipSuccess) return HCOV_EDEVICE;
+  // fixed Gaussian test matrix of the randomised range finder
+  if (launch_gaussian(c->d_buf[B_OMEGA], P.omega_rows * P.rcap, o.seed ? o.seed : 0x5eed5eedULL, c->stream) !=
+      hipSuccess)
+    return HCOV_EDEVICE;
+  // job arrays
+  std::vector<FillJob> fj;
+  std::vector<AcaJob> aj;
+  std::vector<int4> cp;
+  for (auto& B : P.blocks) {
+    if (B.kind == 0) {
+      fj.push_back(FillJob{B.off_d, B.r0, B.c0, int32_t(B.r1 - B.r0), int32_t(B.c1 - B.c0), B.a == B.c ? 1 : 0, 0});
+    } else {
+      aj.push_back(AcaJob{B.off_u, B.off_v, B.r0, B.c0, int32_t(B.r1 - B.r0), int32_t(B.c1 - B.c0), B.rank0_slot,
+                          B.cap, B.need_slot, 0});
+      cp.push_back(make_int4(B.rank_slot, B.rank0_slot, B.hint_slot, B.cand_slot));
+    }
+  }
+  // blocks with more than ACA_BIG_SPLIT rows + columns: multi-work-group ACA
+  const int ACA_BIG_SPLIT = 2048;
+  std::vector<AcaJob> big, small;
+  for (auto& a : aj) (int64_t(a.p) + a.q > ACA_BIG_SPLIT ? big : small).push_back(a);
+  std::stable_sort(small.begin(), small.end(), [](const AcaJob& a, const AcaJob& b) {
+    return int64_t(a.p) + a.q > int64_t(b.p) + b.q;
+  });
+  aj = small;
+  {
+    std::vector<AcaBigChunk> rows, cols;
+    std::vector<int> rf, rcn, cf, ccn;
+    for (int b = 0; b < int(big.size()); ++b) {
+      rf.push_back(int(rows.size()));
+      for (int c0 = 0; c0 < big[b].q; c0 += ACA_BIG_CHUNK) rows.push_back(AcaBigChunk{b, c0});
+      rcn.push_back(int(rows.size()) - rf.back());
+      cf.push_back(int(cols.size()));
+      for (int c0 = 0; c0 < big[b].p; c0 += ACA_BIG_CHUNK) cols.push_back(AcaBigChunk{b, c0});
+      ccn.push_back(int(cols.size()) - cf.back());
+    }
+    c->n_acab = int(big.size());
+    c->n_brow = int(rows.size());
+    c->n_bcol = int(cols.size());
+    if (c->n_acab > 0) {
+      c->d_acab = upload(c, big);
+      c->d_brow = upload(c, rows);
+      c->d_bcol = upload(c, cols);
+      c->d_brow_first = upload(c, rf);
+      c->d_brow_count = upload(c, rcn);
+      c->d_bcol_first = upload(c, cf);
+      c->d_bcol_count = upload(c, ccn);
+      c->d_bstate = (AcaBigState*)dev_alloc(c, size_t(c->n_acab) * ACA_BIG_STATE_BYTES);
+      c->d_bpart = (double*)dev_alloc(c, size_t(std::max(c->n_brow, c->n_bcol)) * ACA_BIG_PREC * 8);
+      c->d_bacc = (double*)dev_alloc(c, size_t(c->n_acab) * ACA_BIG_PREC * 8);
+      c->d_bactive = (int*)dev_alloc(c, 16);
+      if (!c->d_acab || !c->d_brow || !c->d_bcol || !c->d_brow_first || !c->d_brow_count || !c->d_bcol_first ||
+          !c->d_bcol_count || !c->d_bstate || !c->d_bpart || !c->d_bacc || !c->d_bactive)
+        return HCOV_ENOMEM;
+    }
+  }
+  c->n_fill = int(fj.size());
+  c->n_aca = int(aj.size());
+  c->d_fill = upload(c, fj);
+  c->d_aca = upload(c, aj);
+  c->L = LaunchCtx{};
+  LaunchCtx& L = c->L;
+  for (int b = 0; b < B_COUNT; ++b) L.bufs.p[b] = c->d_buf[b];
+  std::vector<Bufs> btab(1, L.bufs);
+  L.dbufs = upload(c, btab);
+  L.dyn = c->d_dyn;
+  L.gjobs = upload(c, P.gjobs);
+  L.gprods = upload(c, P.gprods);
+  L.gtiles = upload(c, P.gtiles);
+  L.tsegs = upload(c, P.tsegs);
+  L.treds = upload(c, P.treds);
+  L.smalls = upload(c, P.smalls);
+  L.leafs = upload(c, P.leafs);
+  L.trsms = upload(c, P.trsms);
+  L.copy_pairs = upload(c, cp);
+  L.n_copy = int(cp.size());
+  L.rmax = P.rmax;
+  L.oversample = o.oversample;
+  L.fixed_rank = o.fixed_rank;
+  // FP32 accumulation leaves noise of order 1e-7 relative in the low-rank
+  // products: in mixed precision the truncations keep singular values above
+  // max(eps, 1e-6) of the largest, so that noise is not kept as rank
+  L.eps = o.precision == HCOV_MIXED ? std::max(c->eps, MIXED_EPS_FLOOR) : c->eps;
+  L.tau = std::min(1e-10, 1e-2 * c->eps);
+  L.logdet = c->d_logdet;
+  L.status = c->d_status;
+  if (!L.dbufs || !L.gjobs || !L.gprods || !L.gtiles || !L.tsegs || !L.treds || !L.smalls || !L.leafs ||
+      !L.trsms || !L.copy_pairs || !c->d_fill || !c->d_aca)
+    return HCOV_ENOMEM;
+  if (c->keep) {
+    // the launch context of the kept C~: its own arenas and dimensions
+    c->Lc = L;
+    c->Lc.bufs.p[B_DENSE] = c->d_keep[0];
+    c->Lc.bufs.p[B_U] = c->d_keep[1];
+    c->Lc.bufs.p[B_V] = c->d_keep[2];
+    std::vector<Bufs> kt(1, c->Lc.bufs);
+    c->Lc.dbufs = upload(c, kt);
+    c->Lc.dyn = c->d_dyn_keep;
+    if (!c->Lc.dbufs) return HCOV_ENOMEM;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return HCOV_EDEVICE;
+  c->plan_ok = true;
+  return HCOV_OK;
+}
+
+// Gives back everything setup_plan allocated (after the streams drained)
+// and drops the captured sweep and any pending profiling events.
+int release_plan(hcov_ctx* c) {
+  if (c->stream2) HIPCHK(c, hipStreamSynchronize(c->stream2));
+  if (c->gstream) HIPCHK(c, hipStreamSynchronize(c->gstream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->plan_ok = false;
+  for (auto g : c->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  c->gexec.clear();
+  for (auto& ev : c->prof_ev) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  c->prof_ev.clear();
+  c->prof_stages.clear();
+  c->prof_where.clear();
+  for (size_t i = c->allocs.size(); i-- > c->n_base_allocs;) {
+    if (c->opts.free)
+      c->opts.free(c->allocs[i], c->opts.alloc_user);
+    else
+      (void)hipFree(c->allocs[i]);
+    c->bytes -= int64_t(c->alloc_bytes[i]);
+  }
+  c->allocs.resize(c->n_base_allocs);
+  c->alloc_bytes.resize(c->n_base_allocs);
+  for (auto& b : c->d_buf) b = nullptr;
+  c->d_dyn = c->d_status = nullptr;
+  c->d_logdet = c->d_part = c->d_tmp = nullptr;
+  c->d_fill = nullptr;
+  c->d_aca = c->d_acab = nullptr;
+  c->n_fill = c->n_aca = c->n_acab = c->n_brow = c->n_bcol = 0;
+  c->d_brow = c->d_bcol = nullptr;
+  c->d_brow_first = c->d_brow_count = c->d_bcol_first = c->d_bcol_count = nullptr;
+  c->d_bstate = nullptr;
+  c->d_bpart = c->d_bacc = nullptr;
+  c->d_bactive = nullptr;
+  for (auto& k : c->d_keep) k = nullptr;
+  c->d_dyn_keep = nullptr;
+  c->d_vec = nullptr;
+  c->L = LaunchCtx{};
+  c->Lc = LaunchCtx{};
+  c->kept_valid = false;
+  return HCOV_OK;
+}
+
+// Rebuilds the plan at the grown capacities.  The dynamic slots keep their
+// numbering (it depends on the trees only), so the rank hints carry over;
+// the need slots start again from zero.  C~ must be assembled again.
+int replan(hcov_ctx* c) {
+  const int32_t n_dyn = c->plan.n_dyn;
+  std::vector<int> dyn(size_t(n_dyn) + 1);
+  HIPCHK(c, hipMemcpyAsync(dyn.data(), c->d_dyn, dyn.size() * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int r = release_plan(c);
+  if (r) return r;
+  r = setup_plan(c);
+  if (r) {
+    c->plan_ok = false;
+    return r;
+  }
+  if (c->plan.n_dyn != n_dyn) {
+    c->plan_ok = false;
+    return fail(c, HCOV_EDEVICE, "plan rebuild changed the dynamic slots");
+  }
+  for (const auto& B : c->plan.blocks)
+    if (B.kind == 1) dyn[B.need_slot] = 0;
+  HIPCHK(c, hipMemcpyAsync(c->d_dyn, dyn.data(), dyn.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->assembled = c->factored = false;
+  c->tuned = false;   // the rebuilt stages carry the planner's kernel choice
+  c->n_switched = 0;
+  c->n_replans += 1;
+  return HCOV_OK;
+}
+
+// Assembly, repeated after each capacity growth it triggers.
+int assemble_grown(hcov_ctx* c) {
+  for (int g = 0;; ++g) {
+    int r = assemble(c);
+    if (r != GROW_REPLAN) return r;
+    if (g >= MAX_REPLANS)
+      return fail(c, HCOV_ERANK, "block rank capacities still growing after " + std::to_string(MAX_REPLANS) +
+                                     " plan rebuilds");
+    r = replan(c);
+    if (r) return r;
+  }
 }
 
 }  // namespace
@@ -666,6 +1002,7 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
   if (o.fixed_rank < 0 || o.fixed_rank > o.max_rank) return HCOV_EINVAL;
   if (o.adm_rule != HCOV_ADM_MIN && o.adm_rule != HCOV_ADM_MAX && o.adm_rule != HCOV_ADM_WEAK) return HCOV_EINVAL;
   if (o.autotune != 0 && o.autotune != 1) return HCOV_EINVAL;
+  if (o.initial_rank_cap < 0 || o.initial_rank_cap > o.max_rank) return HCOV_EINVAL;
   std::vector<double> h(2 * n);
   for (int64_t i = 0; i < 2 * n; ++i) {
     if (!std::isfinite(locs[i])) return HCOV_EINVAL;
@@ -761,148 +1098,17 @@ int hcov_build(const double* locs, int64_t n, hcov_theta theta, double eps, int 
     (void)hipFreeAsync(T.d_perm, c->stream);
     hipStreamSynchronize(c->stream);
   }
-  // plan
-  int64_t nb = int64_t(c->blocks_lac.size() / 4);
-  e = build_plan(c->plan, n, c->D, leaf, c->blocks_lac.data(), nb, o.max_rank, o.precision == HCOV_MIXED);
-  if (!e.empty()) {
-    c->err = e;
-    return bail(HCOV_EINVAL);
+  c->n_base_allocs = c->allocs.size();
+  c->sizing = o.initial_rank_cap > 0 && o.fixed_rank == 0;
+  if (c->sizing) {
+    const int64_t nb = int64_t(c->blocks_lac.size() / 4);
+    c->caps.assign(size_t(nb), int32_t(std::min(o.initial_rank_cap, o.max_rank)));
   }
-  Plan& P = c->plan;
-  // memory estimate check
-  size_t need = size_t(P.dense_elems + P.u_elems + P.v_elems + P.scr_elems + P.pers_elems + P.omega_rows * P.rcap +
-                       2 * P.rhs_ld + P.linv_elems) * 8;
-  if (c->keep) need += size_t(P.dense_elems + P.u_elems + P.v_elems + 6 * n) * 8;
-  if (o.mem_cap_bytes && need > o.mem_cap_bytes) {
-    c->err = "estimate " + std::to_string(need) + " bytes exceeds the memory cap";
-    return bail(HCOV_ENOMEM);
-  }
-  c->d_buf[B_DENSE] = (double*)dev_alloc(c, P.dense_elems * 8);
-  c->d_buf[B_U] = (double*)dev_alloc(c, P.u_elems * 8);
-  c->d_buf[B_V] = (double*)dev_alloc(c, P.v_elems * 8);
-  c->d_buf[B_SCR] = (double*)dev_alloc(c, P.scr_elems * 8);
-  c->d_buf[B_OMEGA] = (double*)dev_alloc(c, P.omega_rows * P.rcap * 8);
-  c->d_buf[B_RHS] = (double*)dev_alloc(c, 2 * P.rhs_ld * 8);
-  c->d_buf[B_PERS] = (double*)dev_alloc(c, P.pers_elems * 8);
-  c->d_buf[B_LINV] = (double*)dev_alloc(c, P.linv_elems * 8);
-  c->d_dyn = (int*)dev_alloc(c, (P.n_dyn + 1) * 4);
-  c->d_status = (int*)dev_alloc(c, 16);
-  int64_t m = int64_t(1) << c->D;
-  c->d_logdet = (double*)dev_alloc(c, m * 8);
-  c->d_part = (double*)dev_alloc(c, ((n + 1023) / 1024 + m / 1024 + 8) * 8);
-  c->d_tmp = (double*)dev_alloc(c, n * 8);
-  for (int b = 0; b < B_COUNT; ++b)
-    if (!c->d_buf[b]) return bail(HCOV_ENOMEM);
-  if (c->keep) {
-    c->d_keep[0] = (double*)dev_alloc(c, P.dense_elems * 8);
-    c->d_keep[1] = (double*)dev_alloc(c, P.u_elems * 8);
-    c->d_keep[2] = (double*)dev_alloc(c, P.v_elems * 8);
-    c->d_dyn_keep = (int*)dev_alloc(c, (P.n_dyn + 1) * 4);
-    c->d_vec = (double*)dev_alloc(c, 6 * n * 8);
-    if (!c->d_keep[0] || !c->d_keep[1] || !c->d_keep[2] || !c->d_dyn_keep || !c->d_vec) return bail(HCOV_ENOMEM);
-  }
-  if (!c->d_dyn || !c->d_status || !c->d_logdet || !c->d_part || !c->d_tmp) return bail(HCOV_ENOMEM);
-  hipMemsetAsync(c->d_dyn, 0, (P.n_dyn + 1) * 4, c->stream);
-  // fixed Gaussian test matrix of the randomised range finder
-  if (launch_gaussian(c->d_buf[B_OMEGA], P.omega_rows * P.rcap, o.seed ? o.seed : 0x5eed5eedULL, c->stream) !=
-      hipSuccess)
-    return bail(HCOV_EDEVICE);
-  // job arrays
-  std::vector<FillJob> fj;
-  std::vector<AcaJob> aj;
-  std::vector<int4> cp;
-  for (auto& B : P.blocks) {
-    if (B.kind == 0) {
-      fj.push_back(FillJob{B.off_d, B.r0, B.c0, int32_t(B.r1 - B.r0), int32_t(B.c1 - B.c0), B.a == B.c ? 1 : 0, 0});
-    } else {
-      aj.push_back(AcaJob{B.off_u, B.off_v, B.r0, B.c0, int32_t(B.r1 - B.r0), int32_t(B.c1 - B.c0), B.rank0_slot, 0});
-      cp.push_back(make_int4(B.rank_slot, B.rank0_slot, B.hint_slot, B.cand_slot));
-    }
-  }
-  // blocks with more than ACA_BIG_SPLIT rows + columns: multi-work-group ACA
-  const int ACA_BIG_SPLIT = 2048;
-  std::vector<AcaJob> big, small;
-  for (auto& a : aj) (int64_t(a.p) + a.q > ACA_BIG_SPLIT ? big : small).push_back(a);
-  std::stable_sort(small.begin(), small.end(), [](const AcaJob& a, const AcaJob& b) {
-    return int64_t(a.p) + a.q > int64_t(b.p) + b.q;
-  });
-  aj = small;
   {
-    std::vector<AcaBigChunk> rows, cols;
-    std::vector<int> rf, rcn, cf, ccn;
-    for (int b = 0; b < int(big.size()); ++b) {
-      rf.push_back(int(rows.size()));
-      for (int c0 = 0; c0 < big[b].q; c0 += ACA_BIG_CHUNK) rows.push_back(AcaBigChunk{b, c0});
-      rcn.push_back(int(rows.size()) - rf.back());
-      cf.push_back(int(cols.size()));
-      for (int c0 = 0; c0 < big[b].p; c0 += ACA_BIG_CHUNK) cols.push_back(AcaBigChunk{b, c0});
-      ccn.push_back(int(cols.size()) - cf.back());
-    }
-    c->n_acab = int(big.size());
-    c->n_brow = int(rows.size());
-    c->n_bcol = int(cols.size());
-    if (c->n_acab > 0) {
-      c->d_acab = upload(c, big);
-      c->d_brow = upload(c, rows);
-      c->d_bcol = upload(c, cols);
-      c->d_brow_first = upload(c, rf);
-      c->d_brow_count = upload(c, rcn);
-      c->d_bcol_first = upload(c, cf);
-      c->d_bcol_count = upload(c, ccn);
-      c->d_bstate = (AcaBigState*)dev_alloc(c, size_t(c->n_acab) * ACA_BIG_STATE_BYTES);
-      c->d_bpart = (double*)dev_alloc(c, size_t(std::max(c->n_brow, c->n_bcol)) * ACA_BIG_PREC * 8);
-      c->d_bacc = (double*)dev_alloc(c, size_t(c->n_acab) * ACA_BIG_PREC * 8);
-      c->d_bactive = (int*)dev_alloc(c, 16);
-      if (!c->d_acab || !c->d_brow || !c->d_bcol || !c->d_brow_first || !c->d_brow_count || !c->d_bcol_first ||
-          !c->d_bcol_count || !c->d_bstate || !c->d_bpart || !c->d_bacc || !c->d_bactive)
-        return bail(HCOV_ENOMEM);
-    }
+    const int rs = setup_plan(c);
+    if (rs) return bail(rs);
   }
-  c->n_fill = int(fj.size());
-  c->n_aca = int(aj.size());
-  c->d_fill = upload(c, fj);
-  c->d_aca = upload(c, aj);
-  LaunchCtx& L = c->L;
-  for (int b = 0; b < B_COUNT; ++b) L.bufs.p[b] = c->d_buf[b];
-  std::vector<Bufs> btab(1, L.bufs);
-  L.dbufs = upload(c, btab);
-  L.dyn = c->d_dyn;
-  L.gjobs = upload(c, P.gjobs);
-  L.gprods = upload(c, P.gprods);
-  L.gtiles = upload(c, P.gtiles);
-  L.tsegs = upload(c, P.tsegs);
-  L.treds = upload(c, P.treds);
-  L.smalls = upload(c, P.smalls);
-  L.leafs = upload(c, P.leafs);
-  L.trsms = upload(c, P.trsms);
-  L.copy_pairs = upload(c, cp);
-  L.n_copy = int(cp.size());
-  L.rmax = P.rmax;
-  L.oversample = o.oversample;
-  L.fixed_rank = o.fixed_rank;
-  // FP32 accumulation leaves noise of order 1e-7 relative in the low-rank
-  // products: in mixed precision the truncations keep singular values above
-  // max(eps, 1e-6) of the largest, so that noise is not kept as rank
-  L.eps = o.precision == HCOV_MIXED ? std::max(eps, MIXED_EPS_FLOOR) : eps;
-  L.tau = std::min(1e-10, 1e-2 * eps);
-  L.logdet = c->d_logdet;
-  L.status = c->d_status;
-  if (!L.dbufs || !L.gjobs || !L.gprods || !L.gtiles || !L.tsegs || !L.treds || !L.smalls || !L.leafs ||
-      !L.trsms || !L.copy_pairs || !c->d_fill || !c->d_aca)
-    return bail(HCOV_ENOMEM);
-  if (c->keep) {
-    // the launch context of the kept C~: its own arenas and dimensions
-    c->Lc = L;
-    c->Lc.bufs.p[B_DENSE] = c->d_keep[0];
-    c->Lc.bufs.p[B_U] = c->d_keep[1];
-    c->Lc.bufs.p[B_V] = c->d_keep[2];
-    std::vector<Bufs> kt(1, c->Lc.bufs);
-    c->Lc.dbufs = upload(c, kt);
-    c->Lc.dyn = c->d_dyn_keep;
-    if (!c->Lc.dbufs) return bail(HCOV_ENOMEM);
-  }
-  if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(HCOV_EDEVICE);
-  int r = assemble(c);
+  int r = assemble_grown(c);
   if (r != HCOV_OK && r != HCOV_ERANK) {
     std::string keep = c->err;
     hcov_destroy(c);
@@ -918,7 +1124,7 @@ int hcov_set_theta(hcov_ctx* c, hcov_theta theta) {
   if (!theta_ok(theta)) return fail(c, HCOV_EINVAL, "theta out of domain");
   c->theta = theta;
   c->assembled = c->factored = false;
-  return assemble(c);
+  return assemble_grown(c);
 }
 
 int hcov_cholesky(hcov_ctx* c) {
@@ -1311,6 +1517,8 @@ int hcov_stats(const hcov_ctx* c, hcov_stats_t* s) {
     s->gemm_flops_factor = fl;
     s->gemm_bytes_factor = by;
   }
+  s->n_replans = c->n_replans;
+  s->bytes_lowrank = (P.u_elems + P.v_elems) * 8;
   {
     // sketch width of every low-rank block in the last factorisation
     double w = 0.0;

@@ -1845,7 +1845,10 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
       }
       if (fixed_rank > 0) kk = min(kk, fixed_rank);
       if (kk > J.cap) {
-        if (lane == 0) atomicOr(status, STAT_RANK_OVERFLOW);
+        if (lane == 0) {
+          atomicOr(status, STAT_RANK_OVERFLOW);
+          if (J.need_slot >= 0) atomicMax(dyn + J.need_slot, kk);
+        }
         kk = J.cap;
       }
       if (lane == 0) sketch_report(J, dyn, kk, status);
@@ -1919,7 +1922,10 @@ __global__ __launch_bounds__(256) void k_small(const Bufs* __restrict__ bufs, in
   }
   if (fixed_rank > 0) kk = min(kk, fixed_rank);
   if (kk > J.cap) {
-    if (tid == 0) atomicOr(status, STAT_RANK_OVERFLOW);
+    if (tid == 0) {
+      atomicOr(status, STAT_RANK_OVERFLOW);
+      if (J.need_slot >= 0) atomicMax(dyn + J.need_slot, kk);
+    }
     kk = J.cap;
   }
   if (J.kind == SK_SKETCH_F && tid == 0) sketch_report(J, dyn, kk, status);
@@ -2481,7 +2487,7 @@ __global__ __launch_bounds__(256) void k_aca(double* __restrict__ Ub, double* __
   int i = 0;
   int k = 0;
   double nrm2 = 0.0;
-  const int kmax = min(min(p, q), kcap);
+  const int kmax = min(min(p, q), min(kcap, J.cap));
   int attempts = 0;
   while (k < kmax && attempts < p + 1) {
     ++attempts;
@@ -2583,7 +2589,10 @@ __global__ __launch_bounds__(256) void k_aca(double* __restrict__ Ub, double* __
     }
     i = ni;
   }
-  if (k == kmax && kmax < min(p, q) && !cap_ok && tid == 0) atomicOr(status, STAT_RANK_OVERFLOW);
+  if (k == kmax && kmax < min(p, q) && !cap_ok && tid == 0) {
+    atomicOr(status, STAT_RANK_OVERFLOW);
+    if (J.need_slot >= 0) atomicMax(dyn + J.need_slot, kmax + 1);
+  }
   if (tid == 0) dyn[J.rank_slot] = k;
   (void)dots;
 }

@@ -20,6 +20,8 @@ struct AcaJob {
   int64_t r0, c0;
   int32_t p, q;
   int32_t rank_slot;
+  int32_t cap;         // rank capacity of the block's arenas (<= the launch's kcap)
+  int32_t need_slot;   // dyn slot raised to cap + 1 when the approximation stops at cap unconverged
   int32_t pad;
 };
 

@@ -327,7 +327,7 @@ class Builder {
     abort();
   }
 
-  Dim rank_dim(int32_t b) const { return dim_dyn(P.blocks[b].rank_slot, P.kcap); }
+  Dim rank_dim(int32_t b) const { return dim_dyn(P.blocks[b].rank_slot, P.blocks[b].cap); }
 
   // U of block b restricted to absolute rows [r0, r1)
   Src lr_u(int32_t b, int64_t r0) const {
@@ -956,7 +956,8 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         J.R1 = Ref{B_SCR, RM, s.rb};
         J.R2 = Ref{B_SCR, RM, s.rq};
         J.C1 = Ref{B_SCR, RM, s.c2};
-        J.cap = P.kcap;
+        J.cap = P.blocks[s.b].cap;
+        J.need_slot = P.blocks[s.b].need_slot;
         J.sat = s.r;            // saturation if the kept rank nearly fills r
         J.full = int32_t(std::min(s.p, s.q));
         J.cand_slot = P.blocks[s.b].cand_slot;
@@ -1057,7 +1058,7 @@ void Builder::build_recompress() {
     pers_max = std::max(pers_max, pers);
     for (size_t i = c0; i < c1; ++i) {
       const BlockInfo& B = P.blocks[lrb[i]];
-      Dim k0 = dim_dyn(B.rank0_slot, P.kcap);
+      Dim k0 = dim_dyn(B.rank0_slot, B.cap);
       tsqr(Ref{B_U, int32_t(B.r1 - B.r0), B.off_u}, B.r1 - B.r0, k0, Ref{B_PERS, RM, ru[i - c0]});
       tsqr(Ref{B_V, int32_t(B.c1 - B.c0), B.off_v}, B.c1 - B.c0, k0, Ref{B_PERS, RM, rv[i - c0]});
     }
@@ -1068,12 +1069,12 @@ void Builder::build_recompress() {
       SmallJob J{};
       J.kind = SK_RECOMP;
       J.out_rank_slot = B.rank_slot;
-      J.k = dim_dyn(B.rank0_slot, P.kcap);
+      J.k = dim_dyn(B.rank0_slot, B.cap);
       J.R1 = Ref{B_PERS, RM, ru[i - c0]};
       J.R2 = Ref{B_PERS, RM, rv[i - c0]};
       J.C1 = Ref{B_PERS, RM, cu[i - c0]};
       J.C2 = Ref{B_PERS, RM, cv[i - c0]};
-      J.cap = P.kcap;
+      J.cap = B.cap;
       J.sat = dim_static(-1);
       J.full = 0;
       J.cand_slot = -1;
@@ -1083,7 +1084,7 @@ void Builder::build_recompress() {
     flush_small(P.recomp_stages, sm0);
     for (size_t i = c0; i < c1; ++i) {
       const BlockInfo& B = P.blocks[lrb[i]];
-      Dim k0 = dim_dyn(B.rank0_slot, P.kcap);
+      Dim k0 = dim_dyn(B.rank0_slot, B.cap);
       int32_t d = defer(listA, Ref{B_U, int32_t(B.r1 - B.r0), B.off_u},
                         dim_static(int(B.r1 - B.r0)), rank_dim(lrb[i]), 1);
       dprod(listA[d], Ref{B_U, int32_t(B.r1 - B.r0), B.off_u}, 0, Ref{B_PERS, RM, cu[i - c0]}, 0,
@@ -1242,7 +1243,7 @@ void Builder::build_matvec() {
 }  // namespace
 
 std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, int64_t nb,
-                       int kcap, bool mixed) {
+                       int kcap, bool mixed, const int32_t* caps) {
   P = Plan();
   P.mixed = mixed;
   P.n = n;
@@ -1286,22 +1287,26 @@ std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blk, 
     B.c1 = P.lo[B.level][B.c + 1];
     int64_t p = B.r1 - B.r0, q = B.c1 - B.c0;
     if (B.kind == 1) {
+      B.cap = caps ? caps[b] : kcap;
+      if (B.cap < 1 || B.cap > kcap) return "block rank capacity outside [1, kcap]";
       B.off_u = P.u_elems;
-      P.u_elems += p * kcap;
+      P.u_elems += p * B.cap;
       B.off_v = P.v_elems;
-      P.v_elems += q * kcap;
+      P.v_elems += q * B.cap;
       B.off_d = -1;
       B.rank_slot = dyn++;
       B.rank0_slot = dyn++;
       B.hint_slot = dyn++;
       B.cand_slot = dyn++;
+      B.need_slot = dyn++;
       P.n_lr++;
       P.lr_rows += p + q;
     } else {
       B.off_d = P.dense_elems;
       P.dense_elems += p * q;
       B.off_u = B.off_v = -1;
-      B.rank_slot = B.rank0_slot = B.hint_slot = B.cand_slot = -1;
+      B.rank_slot = B.rank0_slot = B.hint_slot = B.cand_slot = B.need_slot = -1;
+      B.cap = 0;
       P.n_dense++;
       if (B.level != D) return "dense block above the leaf level";
       if (B.a == B.c) P.diag_block[B.a] = int32_t(b);

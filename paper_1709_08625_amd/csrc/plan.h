@@ -108,6 +108,8 @@ struct SmallJob {
                            // the whole column space and cannot saturate
   int32_t cand_slot;       // dyn slot of the block's candidate rank hint (-1: none)
   double eps;              // < 0: taken from the launch (-1 eps, -2 tau)
+  int32_t need_slot = -1;  // dyn slot receiving the untruncated count when it exceeds cap (-1: none)
+  int32_t pad = 0;
 };
 
 // ---------------------------------------------------------------- leaf jobs
@@ -163,6 +165,8 @@ struct BlockInfo {
   int32_t rank0_slot;          // dyn slot of the ACA rank, then of the sketch width (LR)
   int32_t hint_slot;           // dyn slot of the rank hint of the sweep's sketch width (LR)
   int32_t cand_slot;           // dyn slot of the rank the last factorisation kept (LR)
+  int32_t cap;                 // columns of the block's U and V arenas (LR): its rank capacity
+  int32_t need_slot;           // dyn slot of the largest rank a truncation or the ACA asked beyond cap (LR)
 };
 
 struct Plan {
@@ -227,8 +231,10 @@ inline uint64_t key3(int l, int64_t a, int64_t c) {
 // after a factorisation that saturated, so that the widths, and with them
 // the results, change only when a sketch was too narrow.
 constexpr int OVERSAMPLE_MAX = 16;
+// caps: per block (n_blocks entries, read for low-rank blocks) the columns of
+// its U and V arenas, each in [1, kcap]; nullptr gives every block kcap.
 std::string build_plan(Plan& P, int64_t n, int D, int leaf, const int64_t* blocks_lac,
-                       int64_t n_blocks, int kcap, bool mixed);
+                       int64_t n_blocks, int kcap, bool mixed, const int32_t* caps = nullptr);
 
 int64_t node_lo(const Plan& P, int l, int64_t i);
 int64_t node_hi(const Plan& P, int l, int64_t i);

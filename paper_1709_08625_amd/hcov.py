@@ -45,7 +45,8 @@ class Opts(C.Structure):
                 ("free", FREE_FN), ("alloc_user", C.c_void_p), ("use_graphs", C.c_int),
                 ("oversample", C.c_int), ("on_saturation", C.c_int), ("keep_matrix", C.c_int),
                 ("quad_mode", C.c_int), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int), ("fixed_rank", C.c_int),
-                ("adm_rule", C.c_int), ("autotune", C.c_int), ("seed", C.c_uint64)]
+                ("adm_rule", C.c_int), ("autotune", C.c_int), ("seed", C.c_uint64),
+                ("initial_rank_cap", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -58,7 +59,7 @@ class Stats(C.Structure):
                 ("n_sketch_retries", C.c_int64), ("sketch_saturated", C.c_int), ("mean_sketch_width", C.c_double),
                 ("pcg_iters", C.c_int), ("pcg_relres", C.c_double), ("n_gemm_grouped", C.c_int64),
                 ("n_autotune_switched", C.c_int64), ("gemm_flops_factor", C.c_double),
-                ("gemm_bytes_factor", C.c_double)]
+                ("gemm_bytes_factor", C.c_double), ("n_replans", C.c_int64), ("bytes_lowrank", C.c_int64)]
 
 
 _lib = None

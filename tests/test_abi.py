@@ -85,8 +85,9 @@ def test_sketch_options_validated_on_host():
     locs = np.random.default_rng(0).random((100, 2))
     o = hcov.default_opts()
     assert o.oversample == 10 and o.on_saturation == hcov.SAT_RETRY
-    assert o.autotune == 0 and o.seed == 0
-    for bad in ({"oversample": 1}, {"oversample": 65}, {"on_saturation": 2}, {"autotune": 2}):
+    assert o.autotune == 0 and o.seed == 0 and o.initial_rank_cap == 0
+    for bad in ({"oversample": 1}, {"oversample": 65}, {"on_saturation": 2}, {"autotune": 2},
+                {"initial_rank_cap": -1}, {"initial_rank_cap": 65}, {"max_rank": 16, "initial_rank_cap": 17}):
         with pytest.raises(hcov.HcovError) as e:
             hcov.HCov(locs, (1.0, 0.1, 0.5, 1e-4), eps=1e-8, leaf=32, opts=bad)
         assert e.value.code == hcov.EINVAL
