@@ -615,7 +615,7 @@ class Builder {
           dprod(listA[dA], Va.ref, 1, Vb.ref, 0, dim_static(int(K1 - K0)), 0, 0, rank_dim(sR),
                 rank_dim(sP), 1.0);
         }
-        int64_t u = scr_alloc((R1 - R0) * int64_t(P.kcap));
+        int64_t u = scr_alloc((R1 - R0) * int64_t(P.blocks[sP].cap));
         int32_t dB = defer(listB, Ref{B_SCR, int32_t(R1 - R0), u}, dim_static(int(R1 - R0)),
                            rank_dim(sP), 1);
         dprod(listB[dB], Ua.ref, 0, Ref{B_PERS, P.kcap, c}, 0, rank_dim(sR), 0, 0,
@@ -817,7 +817,9 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         s.b = lrs[t].b;
         s.p = B.r1 - B.r0;
         s.q = B.c1 - B.c0;
-        int rmaxT = int(std::min<int64_t>({s.p, s.q, int64_t(P.rcap)}));
+        // the widest sketch a block can use: its capacity plus the oversampling
+        // bound (a wider kept rank overflows the capacity anyway)
+        int rmaxT = int(std::min<int64_t>({s.p, s.q, int64_t(B.cap) + OVERSAMPLE_MAX}));
         // after the assembly the rank0 slot holds rank + oversampling
         s.r = Dim{B.rank0_slot, 0, rmaxT};
         s.rk = dim_dyn(dyn_alloc(), rmaxT);
@@ -831,9 +833,9 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         s.c2 = scr_alloc(RR);
         // P1 = V^T Omega for A and each term
         Dim kA = rank_dim(s.b);
-        int64_t pa = scr_alloc(int64_t(P.kcap) * rmaxT);
+        int64_t pa = scr_alloc(int64_t(B.cap) * rmaxT);
         s.p1.push_back(pa);
-        int32_t d = defer(listA, Ref{B_SCR, P.kcap, pa}, kA, s.r, 1);
+        int32_t d = defer(listA, Ref{B_SCR, B.cap, pa}, kA, s.r, 1);
         dprod(listA[d], Ref{B_V, int32_t(s.q), B.off_v}, 1, Ref{B_OMEGA, int32_t(P.omega_rows), 0},
               0, dim_static(int(s.q)), 0, 0, kA, s.r, 1.0);
         for (auto& T : lrs[t].terms) {
@@ -853,7 +855,7 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         const BlockInfo& B = P.blocks[sk[t].b];
         SK& s = sk[t];
         int32_t d = defer(listB, Ref{B_SCR, int32_t(s.p), s.y}, dim_static(int(s.p)), s.r, 1);
-        dprod(listB[d], Ref{B_U, int32_t(s.p), B.off_u}, 0, Ref{B_SCR, P.kcap, s.p1[0]}, 0,
+        dprod(listB[d], Ref{B_U, int32_t(s.p), B.off_u}, 0, Ref{B_SCR, B.cap, s.p1[0]}, 0,
               rank_dim(s.b), 0, 0, dim_static(int(s.p)), s.r, 1.0);
         for (size_t i = 0; i < lrs[t].terms.size(); ++i) {
           auto& T = lrs[t].terms[i];
@@ -894,9 +896,9 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         const BlockInfo& B = P.blocks[sk[t].b];
         SK& s = sk[t];
         int rmaxT = s.r.maxv;
-        int64_t za = scr_alloc(int64_t(P.kcap) * rmaxT);
+        int64_t za = scr_alloc(int64_t(B.cap) * rmaxT);
         s.z1.push_back(za);
-        int32_t d = defer(listA, Ref{B_SCR, P.kcap, za}, rank_dim(s.b), s.rk, 1);
+        int32_t d = defer(listA, Ref{B_SCR, B.cap, za}, rank_dim(s.b), s.rk, 1);
         dprod(listA[d], Ref{B_U, int32_t(s.p), B.off_u}, 1, Ref{B_SCR, int32_t(s.p), s.qm}, 0,
               dim_static(int(s.p)), 0, 0, rank_dim(s.b), s.rk, 1.0);
         for (auto& T : lrs[t].terms) {
@@ -914,7 +916,7 @@ void Builder::build_steps(bool fuse_rhs, std::vector<std::vector<Stage>>& steps)
         const BlockInfo& B = P.blocks[sk[t].b];
         SK& s = sk[t];
         int32_t d = defer(listB, Ref{B_SCR, int32_t(s.q), s.bp}, dim_static(int(s.q)), s.rk, 1);
-        dprod(listB[d], Ref{B_V, int32_t(s.q), B.off_v}, 0, Ref{B_SCR, P.kcap, s.z1[0]}, 0,
+        dprod(listB[d], Ref{B_V, int32_t(s.q), B.off_v}, 0, Ref{B_SCR, B.cap, s.z1[0]}, 0,
               rank_dim(s.b), 0, 0, dim_static(int(s.q)), s.rk, 1.0);
         for (size_t i = 0; i < lrs[t].terms.size(); ++i) {
           auto& T = lrs[t].terms[i];
