@@ -256,6 +256,8 @@ def large2m(args, hcov, workloads):
     n, truth, nug, leaf, eta, eps = args.n if args.n != 512000 else 2000000, (1.0, 0.1, 0.5), 1e-4, 128, 2.0, 1e-6
     locs, xi = workloads.mixture(n, seed=0)
     opts = {"precision": hcov.MIXED if args.precision == "mixed" else hcov.FP64}
+    if args.rank_cap:
+        opts["initial_rank_cap"] = args.rank_cap
     t0 = time.perf_counter()
     H = hcov.HCov(locs, (*truth, nug), eps=eps, leaf=leaf, eta=eta, opts=opts)
     t_build = time.perf_counter() - t0
@@ -305,7 +307,9 @@ def large2m(args, hcov, workloads):
         "theta_hat": [float(x) for x in theta], "loglik_hat": -float(fbest), "history": hist_all,
         "structure": {"device_GB": st["bytes_device"] / 1e9, "factor_GB": st["bytes_factor"] / 1e9,
                       "max_rank": st["max_rank_seen"], "mean_rank": st["mean_rank"],
-                      "lr_blocks": st["n_lr_blocks"], "dense_blocks": st["n_dense_blocks"]},
+                      "lr_blocks": st["n_lr_blocks"], "dense_blocks": st["n_dense_blocks"],
+                      "initial_rank_cap": args.rank_cap, "lowrank_GB": st["bytes_lowrank"] / 1e9,
+                      "replans": st["n_replans"]},
     }
 
 
