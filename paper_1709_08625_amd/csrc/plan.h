@@ -17,8 +17,8 @@ namespace hc {
 // so plans do not depend on allocation addresses.
 enum BufId : int32_t {
   B_DENSE = 0,   // dense leaves (col-major, one tile per dense block)
-  B_U = 1,       // low-rank U factors, p x kcap col-major per block
-  B_V = 2,       // low-rank V factors, q x kcap col-major per block
+  B_U = 1,       // low-rank U factors, p x cap col-major per block (cap: the block's rank room)
+  B_V = 2,       // low-rank V factors, q x cap col-major per block
   B_SCR = 3,     // per-step scratch (reset every step)
   B_OMEGA = 4,   // fixed Gaussian test matrix (Nmax x rcap col-major)
   B_RHS = 5,     // right-hand side solved inside the sweep (cluster order)
@@ -143,8 +143,9 @@ struct TrsmJob {
 // ---------------------------------------------------------------- stages
 // ST_FORK: the second lane (stream) waits for the work issued so far on the
 // first; ST_JOIN: the first lane waits for the work issued on the second.
-// ST_GEMM_WIDE: the same tiles as ST_GEMM, run by the grouped kernel (four
-// groups of 256 threads per tile) for launches bound by their longest tile.
+// ST_GEMM_WIDE: the same tiles as ST_GEMM, run by the grouped kernel
+// (GEMM_GROUPS groups of 256 threads per tile) for launches bound by their
+// longest tile.
 constexpr int GEMM_GROUPS = 2;   // groups of 256 threads of the grouped GEMM kernel
 enum StageKind : int32_t { ST_GEMM = 0, ST_TSQR_SEG, ST_TSQR_RED, ST_SMALL, ST_LEAF, ST_TRSM, ST_COPY_RANK,
                            ST_FORK, ST_JOIN, ST_TRMM, ST_GEMM_WIDE };
