@@ -92,7 +92,9 @@ typedef struct {
                              rank estimate (the larger of the block's assembled
                              rank and its rank hint, see hcov_cholesky);
                              default 10, range [2, 64]; the width is capped at
-                             max_rank + 16 and at min(rows, cols) of the block */
+                             the block's room + 16 (max_rank + 16 unless
+                             opts.initial_rank_cap sized the rooms) and at
+                             min(rows, cols) of the block */
   int on_saturation;      /* HCOV_SAT_RETRY (default) or HCOV_SAT_ERROR: what a
                              saturated sketch does, see hcov_cholesky */
   int keep_matrix;        /* 1: keep a copy of the assembled C~ (dense and
@@ -254,11 +256,19 @@ int hcov_set_theta(hcov_ctx* ctx, hcov_theta theta);
  * saturated.  With
  * HCOV_SAT_RETRY the matrix is re-assembled and the factorisation redone
  * with the new widths, up to 4 times; a sketch saturated at the widest width
- * (max_rank + 16), saturation after the last retry, or any saturation with
- * HCOV_SAT_ERROR returns HCOV_ERANK.  The factorisation is never reported as
- * done (HCOV_OK) with a saturated sketch.  The hints persist in the context
- * and change only after a saturated factorisation: later factorisations (new
- * theta) start from them, and repeating an evaluation gives the same bits. */
+ * (the block's room + 16), saturation after the last retry, or any
+ * saturation with HCOV_SAT_ERROR returns HCOV_ERANK.  The factorisation is
+ * never reported as done (HCOV_OK) with a saturated sketch.  The hints
+ * persist in the context and change only after a saturated factorisation:
+ * later factorisations (new theta) start from them, and repeating an
+ * evaluation gives the same bits.
+ *
+ * A block whose kept rank exceeds its room (max_rank, or the grown room of
+ * opts.initial_rank_cap) returns HCOV_ERANK when the room is max_rank;
+ * below it the rooms grow, the plan and buffers are rebuilt and the
+ * assembly and factorisation repeat inside this call (at most 8 rebuilds per
+ * call).  Device pointers into the context's buffers are not exposed, so a
+ * rebuild is invisible to the caller except in time and memory. */
 int hcov_cholesky(hcov_ctx* ctx);
 
 /* log|C~| = 2 sum_i log L~_ii [HLIBCov Eq. (2)], FP64 reduction in a fixed

@@ -367,7 +367,7 @@ int check_status(hcov_ctx* c, bool spd_matters) {
     // the error) comes first
     c->factored = false;
     if (st[0] & STAT_SAT_CAP)
-      return fail(c, HCOV_ERANK, "a low-rank block's randomised sketch saturated at the widest width (max_rank + 16)");
+      return fail(c, HCOV_ERANK, "a low-rank block's randomised sketch saturated at the widest width (its room + 16)");
     // the saturated blocks' doubled widths (and every other block's kept rank)
     // become the hints of the next factorisation, retried here or later
     HIPCHK(c, launch_adopt_hints(c->L, c->stream));
