@@ -151,7 +151,11 @@ typedef struct {
                              those at full room up to rounding).  Capacities
                              only grow, over the life of the context.
                              HCOV_ERANK still means a block needs more than
-                             max_rank.  Ignored with fixed_rank > 0. */
+                             max_rank.  A rebuild that does not fit
+                             mem_cap_bytes or the device returns HCOV_ENOMEM
+                             and leaves the context unusable (later calls
+                             return HCOV_ESTATE; destroy it).  Ignored with
+                             fixed_rank > 0. */
 } hcov_opts;
 
 #define HCOV_ADM_MIN 0
