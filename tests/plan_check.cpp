@@ -9,7 +9,10 @@
 // operands of every product (and each product inside its job's extent), TSQR
 // inputs and R slots, the small jobs' R and coefficient slots, the diagonal
 // leaves, the triangular solves' factors and panels, and every low-rank
-// block's U and V.  Prints one summary line; exit status 2 on a violation.
+// block's U and V.  Prints one summary line (with the plan's dynamic-slot
+// and stage counts, which must not depend on the rooms: a context that grows
+// its rooms keeps its rank hints by slot number); exit status 2 on a
+// violation.
 // Compiled with -DSHRINK=b it under-sizes buffer b by one element, so that a
 // test can see the check fail.
 #include <cstdio>
@@ -123,9 +126,11 @@ int main(int argc, char** argv) {
     check("U", Ref{B_U, int32_t(B.r1 - B.r0), B.off_u}, (B.r1 - B.r0) * B.cap - 1, 0);
     check("V", Ref{B_V, int32_t(B.c1 - B.c0), B.off_v}, (B.c1 - B.c0) * B.cap - 1, 0);
   }
+  size_t stages = P.recomp_stages.size();
+  for (const auto& st : P.steps) stages += st.size();
   std::printf("n=%lld rooms %s: %zu GEMM jobs, %zu products, %zu TSQR segments, %zu small jobs; U+V %lld elements; "
-              "violations %ld\n",
+              "dynamic slots %d, stages %zu; violations %ld\n",
               (long long)n, mode.c_str(), P.gjobs.size(), P.gprods.size(), P.tsegs.size(), P.smalls.size(),
-              (long long)(P.u_elems + P.v_elems), g_bad);
+              (long long)(P.u_elems + P.v_elems), P.n_dyn, stages, g_bad);
   return g_bad ? 2 : 0;
 }

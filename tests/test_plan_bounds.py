@@ -75,10 +75,14 @@ def _block_file(tmp_path, n, kind, leaf, rule):
 @pytest.mark.parametrize("n,kind,leaf,rule", SHAPES)
 def test_plan_operands_inside_buffers(checker, tmp_path, n, kind, leaf, rule):
     path = _block_file(tmp_path, n, kind, leaf, rule)
+    layout = set()
     for rooms in ROOMS:
         r = subprocess.run([str(checker), str(path), rooms], capture_output=True, text=True, timeout=300)
         print(r.stdout.strip())
         assert r.returncode == 0, r.stdout + r.stderr
+        layout.add(r.stdout.split("dynamic slots ")[1].split(";")[0])
+    # a rebuild at grown rooms keeps the slot numbering and the stage sequence
+    assert len(layout) == 1, layout
 
 
 def test_checker_sees_an_undersized_buffer(tmp_path):
