@@ -226,7 +226,8 @@ inline uint64_t key3(int l, int64_t a, int64_t c) {
 // Returns an empty string on success, else an error message.
 // The sketch width of a low-rank target is the larger of its assembly rank
 // and its rank hint, plus an oversampling chosen at run time (see
-// ST_COPY_RANK), at most rcap = kcap + OVERSAMPLE_MAX.  A factorisation
+// ST_COPY_RANK), at most the block's room + OVERSAMPLE_MAX (rcap = kcap +
+// OVERSAMPLE_MAX for a block at the full room).  A factorisation
 // writes every target's kept rank (doubled sketch width where the sketch
 // saturated) as its candidate hint; the candidates become the hints only
 // after a factorisation that saturated, so that the widths, and with them
